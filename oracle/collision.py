@@ -1,0 +1,260 @@
+"""Collision operators (test infrastructure only; see ``oracle/__init__.py``).
+
+Every operator maps pre-collision populations f (shape (Q, ...)) to
+post-collision populations, in float64, with no blocking or fusion.
+
+Rates are passed as a plain dict with keys
+    omega       SRT rate; TRT even rate; MRT/cumulant shear rate
+    omega_bulk  MRT/cumulant bulk rate
+    omega_odd   TRT odd rate (<= 0: derived from ``magic``)
+    magic       TRT parameter Lambda = (1/omega_e - 1/2)(1/omega_o - 1/2)
+    omega_hi    MRT/cumulant rates of the moment orders 3, 4, 5, 6
+"""
+
+import functools
+import math
+
+import numpy as np
+
+from .equilibrium import equilibrium, guo_source, macroscopic
+from .lattice import CS2
+from .moments import monomial_exponents, orthogonal_mrt_basis, raw_moment_matrix
+
+
+def trt_odd_rate(rates):
+    """Odd TRT rate: given directly, or from Lambda = (1/w_e - 1/2)(1/w_o - 1/2)."""
+    if rates.get("omega_odd", 0.0) > 0.0:
+        return rates["omega_odd"]
+    we = rates["omega"]
+    return 1.0 / (rates["magic"] / (1.0 / we - 0.5) + 0.5)
+
+
+def srt(lat, f, rates, force=None, rho0=1.0, compressible=True):
+    """Eq. (1): f* = f - omega (f - f^eq), plus Guo's (1 - omega/2) S."""
+    om = rates["omega"]
+    rho, u = macroscopic(lat, f, force, rho0, compressible)
+    feq = equilibrium(lat, rho, u, rho0, compressible)
+    out = f - om * (f - feq)
+    if force is not None:
+        out = out + (1.0 - 0.5 * om) * guo_source(lat, u, force)
+    return out
+
+
+def trt(lat, f, rates, force=None, rho0=1.0, compressible=True):
+    """TRT (Sec. III-C): even moments relax with omega_e, odd with omega_o.
+
+    Written in the equivalent population form: even moments vanish on the
+    antisymmetric part f^- = (f_q - f_opp(q))/2 and odd moments on the
+    symmetric part f^+, so relaxing the two parts with omega_e / omega_o is
+    the same operator.  The Guo source is split the same way.
+    """
+    we = rates["omega"]
+    wo = trt_odd_rate(rates)
+    rho, u = macroscopic(lat, f, force, rho0, compressible)
+    feq = equilibrium(lat, rho, u, rho0, compressible)
+    o = lat.opp
+    fp, fm = 0.5 * (f + f[o]), 0.5 * (f - f[o])
+    ep, em = 0.5 * (feq + feq[o]), 0.5 * (feq - feq[o])
+    out = f - we * (fp - ep) - wo * (fm - em)
+    if force is not None:
+        S = guo_source(lat, u, force)
+        out = out + (1.0 - 0.5 * we) * 0.5 * (S + S[o]) + (1.0 - 0.5 * wo) * 0.5 * (S - S[o])
+    return out
+
+
+def maxwellian_moments(exps, rho, u):
+    """Float version of ``equilibrium.gaussian_raw_moment`` over cell arrays:
+    per-axis Maxwellian moments (1, u_a, c_s^2 + u_a^2) multiplied out with
+    every term above second order in u dropped."""
+    out = []
+    for e in exps:
+        terms = [(0, np.ones_like(rho))]
+        for a, ea in enumerate(e):
+            if ea == 0:
+                fac = [(0, 1.0)]
+            elif ea == 1:
+                fac = [(1, u[a])]
+            else:
+                fac = [(0, CS2), (2, u[a] * u[a])]
+            terms = [(d1 + d2, t1 * t2) for d1, t1 in terms for d2, t2 in fac if d1 + d2 <= 2]
+        out.append(rho * sum(t for _, t in terms))
+    return np.array(out)
+
+
+def trt_moment_form(lat, f, rates):
+    """TRT exactly as the paper builds it (Sec. III-C "SRT, TRT"): raw
+    monomial moments, Maxwellian equilibrium moments truncated at O(u^2), rate
+    omega_e for even and omega_o for odd moments, then Eq. (4).  No forcing.
+    Used as an independent cross-check of ``trt``."""
+    M, exps = raw_moment_matrix(lat)
+    we, wo = rates["omega"], trt_odd_rate(rates)
+    s = np.array([we if sum(e) % 2 == 0 else wo for e in exps])
+    rho, u = macroscopic(lat, f)
+    meq = maxwellian_moments(exps, rho, u)
+    shp = f.shape
+    m = M @ f.reshape(lat.Q, -1)
+    post = m - s[:, None] * (m - meq.reshape(lat.Q, -1))
+    return np.linalg.solve(M, post).reshape(shp)
+
+
+def _group_rates(groups, rates):
+    table = {"o0": 0.0, "o1": 0.0, "shear": rates["omega"], "bulk": rates["omega_bulk"]}
+    for k in range(4):
+        table["o%d" % (k + 3)] = rates["omega_hi"][k]
+    return np.array([table[g] for g in groups])
+
+
+@functools.lru_cache(maxsize=None)
+def _mrt_tables(name):
+    from .lattice import velocity_set
+    lat = velocity_set(name)
+    M, groups, _ = orthogonal_mrt_basis(lat)
+    return M, tuple(groups), np.linalg.inv(M)
+
+
+def mrt(lat, f, rates, force=None, rho0=1.0, compressible=True):
+    """Eq. (4) with the weighted-orthogonal basis of ``moments``.
+
+    m = M f, m^eq = M f^eq (Eq. 3), f* = f - M^-1 S (m - m^eq); the Guo
+    source enters in moment space as M^-1 (I - S/2) M S.  Conserved moments
+    (orders 0, 1) get rate 0, as in the paper's MRT table; with Guo forcing
+    their rate does not change the result.
+    """
+    M, groups, Minv = _mrt_tables(lat.name)
+    s = _group_rates(groups, rates)
+    shp = f.shape
+    rho, u = macroscopic(lat, f, force, rho0, compressible)
+    feq = equilibrium(lat, rho, u, rho0, compressible)
+    f2 = f.reshape(lat.Q, -1)
+    neq = M @ (f2 - feq.reshape(lat.Q, -1))
+    out = f2 - Minv @ (s[:, None] * neq)
+    if force is not None:
+        S = guo_source(lat, u, force).reshape(lat.Q, -1)
+        out = out + Minv @ ((1.0 - 0.5 * s)[:, None] * (M @ S))
+    return out.reshape(shp)
+
+
+def set_partitions(items):
+    """All set partitions of the list ``items`` (blocks are lists)."""
+    if not items:
+        yield []
+        return
+    first, rest = items[0], items[1:]
+    for part in set_partitions(rest):
+        for i in range(len(part)):
+            yield part[:i] + [[first] + part[i]] + part[i + 1:]
+        yield [[first]] + part
+
+
+@functools.lru_cache(maxsize=None)
+def _partitions_of(e):
+    """Set partitions of the multiset x^a y^b z^c, each block returned as
+    its own exponent triple."""
+    labels = [0] * e[0] + [1] * e[1] + [2] * e[2]
+    out = []
+    for part in set_partitions(list(range(len(labels)))):
+        blocks = []
+        for blk in part:
+            cnt = [0, 0, 0]
+            for pos in blk:
+                cnt[labels[pos]] += 1
+            blocks.append(tuple(cnt))
+        out.append(tuple(blocks))
+    return tuple(out)
+
+
+def cumulants_from_moments(mu, exps):
+    """Faa di Bruno / moment-cumulant relation (Sec. III-B).
+
+    ``mu[e]`` are raw moments of the normalised distribution f/rho.  For
+    order >= 1: kappa_S = sum over set partitions pi of S of
+    (-1)^(|pi|-1) (|pi|-1)! prod_{B in pi} mu_B.
+    """
+    kap = {}
+    for e in exps:
+        if sum(e) == 0:
+            continue
+        tot = 0.0
+        for blocks in _partitions_of(e):
+            k = len(blocks)
+            term = (-1.0) ** (k - 1) * math.factorial(k - 1)
+            prod = 1.0
+            for b in blocks:
+                prod = prod * mu[b]
+            tot = tot + term * prod
+        kap[e] = tot
+    return kap
+
+
+def moments_from_cumulants(kap, exps):
+    """Inverse relation: mu_S = sum over set partitions of prod kappa_B."""
+    mu = {}
+    for e in exps:
+        if sum(e) == 0:
+            mu[e] = 1.0
+            continue
+        tot = 0.0
+        for blocks in _partitions_of(e):
+            prod = 1.0
+            for b in blocks:
+                prod = prod * kap[b]
+            tot = tot + prod
+        mu[e] = tot
+    return mu
+
+
+def cumulant(lat, f, rates, force=None, rho0=1.0, compressible=True):
+    """Cumulant collision (Sec. III-B, Eq. 9), D2Q9 and D3Q27.
+
+    populations -> raw moments m_e = sum c^e f (all exponents <= 2)
+    -> cumulants of f/rho (partition formula) -> relaxation
+    kappa* = kappa + omega (kappa^eq - kappa) with the Maxwellian
+    equilibrium: kappa^eq = u (order 1, conserved), c_s^2 delta (order 2),
+    0 (order >= 3).  Order 2 is split into shear (off-diagonal and deviatoric
+    diagonal, rate omega) and bulk (trace, rate omega_bulk); order n >= 3
+    uses omega_hi[n-3].  Then cumulants -> moments -> populations by the
+    inverse of the monomial moment matrix.
+    """
+    if force is not None:
+        raise NotImplementedError("forcing is not defined for the cumulant operator here")
+    if not compressible:
+        raise NotImplementedError("the cumulant operator is compressible by construction")
+    if lat.name not in ("D2Q9", "D3Q27"):
+        raise NotImplementedError("cumulant collision needs a tensor-product stencil")
+    M, exps = raw_moment_matrix(lat)
+    shp = f.shape
+    f2 = f.reshape(lat.Q, -1)
+    m = M @ f2
+    rho = m[exps.index((0, 0, 0))]
+    mu = {e: m[i] / rho for i, e in enumerate(exps)}
+    kap = cumulants_from_moments(mu, exps)
+    om_s, om_b, hi = rates["omega"], rates["omega_bulk"], rates["omega_hi"]
+    D = lat.d
+    post = {}
+    diag = [e for e in exps if sum(e) == 2 and max(e) == 2]
+    tr = sum(kap[e] for e in diag)
+    tr_post = tr + om_b * (D * CS2 - tr)
+    for e in exps:
+        n = sum(e)
+        if n == 0:
+            continue
+        if n == 1:
+            post[e] = kap[e]
+        elif n == 2 and max(e) == 1:
+            post[e] = kap[e] - om_s * kap[e]
+        elif n == 2:
+            dev = kap[e] - tr / D
+            post[e] = (1.0 - om_s) * dev + tr_post / D
+        else:
+            post[e] = kap[e] - hi[n - 3] * kap[e]
+    mu_post = moments_from_cumulants(post, exps)
+    m_post = np.array([rho * mu_post[e] for e in exps])
+    return np.linalg.solve(M, m_post).reshape(shp)
+
+
+OPERATORS = {"SRT": srt, "TRT": trt, "MRT": mrt, "CUMULANT": cumulant}
+
+
+def collide(method, lat, f, rates, force=None, rho0=1.0, compressible=True):
+    """Dispatch on the method name."""
+    return OPERATORS[method](lat, f, rates, force, rho0, compressible)
