@@ -1,0 +1,317 @@
+"""Throughput benchmark of the fused stream-collide sweep on one MI355X.
+
+Headline workload: D3Q19 TRT (Lambda = 3/16, tau_e = 0.8) on a 256^3 channel
+(solid planes y = 0 and y = 255, periodic x and z), constant body force 1e-6
+along x, rho = 1 with seeded uniform +-1e-3 velocity noise, PDFs in FP64.
+A step is one fused stream-pull-collide launch over the whole lattice (the
+inputs are resident in HBM).  The JSON line also carries the FP32-storage
+run of the same workload, the Q-stream copy reference, the D3Q27 cumulant
+(FP32/BF16/FP16 storage, 384^3), the D3Q19 SRT forward+adjoint gradient
+(128^3, FP32, tape every 20 steps) and the D3Q27 MRT (512^3, FP16 vs FP64).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+                       [--no-cpu-baseline]
+"""
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # MI355X HBM3E, bytes/s
+METRIC = "MLUPS & % HBM roofline: D3Q19/D3Q27 fwd+adjoint, FP64 vs FP32/FP16-store"
+BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2001_11806_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name):
+    """Per-launch HBM bytes from a committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Timer:
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __enter__(self):
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.b = self.torch.cuda.Event(enable_timing=True)
+        self.torch.cuda.synchronize()
+        self.a.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record(self.stream)
+        self.torch.cuda.synchronize()
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def run_forward(torch, LBM, inputs, stencil, method, dtype, dims, rates, mask, u, F=None, profile=None,
+                steps=100, warmup=10):
+    lbm = LBM(stencil, method, dtype, dims, rates["omega"], rates.get("omega_bulk", 1.0),
+              rates.get("omega_odd", 0.0), rates.get("magic", 0.0), rates.get("omega_hi", (1.0,) * 4),
+              mask=mask)
+    if F is not None:
+        lbm.set_force(F)
+    if profile is not None:
+        lbm.set_force(profile=profile)
+    lbm.init_equilibrium(None, torch.from_numpy(u))
+    lbm.step(warmup)
+    with Timer(torch, lbm.stream) as t:
+        lbm.step(steps)
+    cells = dims[0] * dims[1] * dims[2]
+    fluid = cells - (int(mask.sum()) if mask is not None else 0)
+    Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[stencil]
+    per_launch = fluid * 2 * Q * BYTES[dtype] + (cells if mask is not None else 0)
+    sec = t.ms / 1e3
+    res = {
+        "mlups": cells * steps / sec / 1e6,
+        "ms_per_step": t.ms / steps,
+        "algorithmic_bytes_per_launch": per_launch,
+        "achieved_GBps": per_launch * steps / sec / 1e9,
+    }
+    res["hbm_frac"] = res["achieved_GBps"] * 1e9 / PEAK_HBM
+    cons = lbm.conserved()
+    res["mass"] = float(cons[0])
+    _, uu = lbm.macroscopic(dtype=torch.float32)
+    res["u_out"] = uu
+    lbm.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,copy,c3,c4,c5)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the multi-GPU halo exchange is not built "
+              "(design only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_11806_amd import inputs
+    from paper_2001_11806_amd.lbm import LBM, copy_q
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_start = time.time()
+
+    # ------------------------------------------------------------ headline
+    n = 256
+    trt = dict(omega=1 / 0.8, magic=3 / 16, omega_odd=0.0)
+    mask, _, u = inputs.channel_flow(n, seed=2, amp=1e-3)
+    F = np.array([1e-6, 0.0, 0.0])
+    log("C2 D3Q19 TRT 256^3 f64: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    head = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f64", (n, n, n), trt, mask, u, F=F,
+                       steps=args.steps, warmup=args.warmup)
+    u64 = head.pop("u_out")
+    log("  %.0f MLUPS, %.0f GB/s" % (head["mlups"], head["achieved_GBps"]))
+    extras = {}
+    only = set(filter(None, args.only.split(",")))
+    want = (lambda k: not args.no_extras and (not only or k in only))
+
+    if want("fp32"):
+        log("C2 D3Q19 TRT 256^3 f32-shifted")
+        r32 = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f32", (n, n, n), trt, mask, u, F=F,
+                          steps=args.steps, warmup=args.warmup)
+        u32 = r32.pop("u_out")
+        fl = torch.from_numpy(mask == 0).to(dev)
+        d = (u32.double() - u64.double())[:, fl]
+        r32["rel_l2_u_vs_f64_same_gpu"] = float(d.norm() / u64.double()[:, fl].norm())
+        extras["c2_d3q19_trt_256_f32"] = r32
+        log("  %.0f MLUPS, rel err u %.2e" % (r32["mlups"], r32["rel_l2_u_vs_f64_same_gpu"]))
+    del u64
+    torch.cuda.empty_cache()
+
+    if want("copy"):
+        for dt, eb in (("f64", 8), ("f32", 4), ("f16", 2)):
+            N = n ** 3
+            src = torch.empty(19 * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
+            dst = torch.empty_like(src)
+            st = torch.cuda.current_stream(dev)
+            for _ in range(3):
+                copy_q(src, dst, N, 19, eb, st)
+            with Timer(torch, st) as t:
+                for _ in range(20):
+                    copy_q(src, dst, N, 19, eb, st)
+            gbps = 2 * 19 * N * eb * 20 / (t.ms / 1e3) / 1e9
+            extras["copy_q19_%s_256" % dt] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
+            log("copy-Q19 %s: %.0f GB/s" % (dt, gbps))
+            del src, dst
+        torch.cuda.empty_cache()
+
+    if want("c3"):
+        n3 = 384
+        log("C3 D3Q27 cumulant 384^3: building solenoidal field")
+        modes = inputs.solenoidal_modes(seed=3)
+        u3 = inputs.solenoidal_velocity(n3, modes, dtype=np.float32)
+        cum = dict(omega=1 / 0.55, omega_bulk=1.0, omega_hi=(1.0,) * 4)
+        ref = None
+        for dt in ("f32", "bf16", "f16"):
+            r = run_forward(torch, LBM, inputs, "D3Q27", "CUMULANT", dt, (n3, n3, n3), cum, None, u3,
+                            steps=50, warmup=5)
+            uo = r.pop("u_out")
+            if ref is None:
+                ref = uo
+            else:
+                r["rel_l2_u_vs_f32_same_gpu_50_steps"] = float((uo - ref).double().norm() / ref.double().norm())
+            extras["c3_d3q27_cumulant_384_%s" % dt] = r
+            log("  %s: %.0f MLUPS, %.0f GB/s" % (dt, r["mlups"], r["achieved_GBps"]))
+        del ref, u3
+        torch.cuda.empty_cache()
+
+    if want("c4"):
+        extras["c4_d3q19_srt_adjoint_128_f32"] = bench_adjoint(torch, LBM, inputs, Timer)
+        torch.cuda.empty_cache()
+
+    if want("c5"):
+        n5 = 512
+        log("C5 D3Q27 MRT 512^3: building noise field")
+        u5 = inputs.uniform_noise_velocity((n5, n5, n5), 1e-3, 5, None, dtype=np.float32)
+        prof = inputs.kolmogorov_force_profile(n5, 1e-6)
+        mrt = dict(omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.0,) * 4)
+        ref = None
+        for dt in ("f64", "f16"):
+            r = run_forward(torch, LBM, inputs, "D3Q27", "MRT", dt, (n5, n5, n5), mrt, None, u5, profile=prof,
+                            steps=20, warmup=3)
+            uo = r.pop("u_out")
+            if ref is None:
+                ref = uo
+            else:
+                r["rel_l2_u_vs_f64_same_gpu_23_steps"] = float((uo - ref).double().norm() / ref.double().norm())
+            extras["c5_d3q27_mrt_512_%s" % dt] = r
+            log("  %s: %.0f MLUPS, %.0f GB/s" % (dt, r["mlups"], r["achieved_GBps"]))
+            del uo
+            torch.cuda.empty_cache()
+        del ref, u5
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inputs)
+
+    traffic = read_traffic("sweep_d3q19_trt_256_f64_traffic.txt")
+    result = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded channel flow (numpy PCG64), no dataset",
+        "config": {"workload": "D3Q19 TRT (magic 3/16, tau 0.8) 256^3 channel, bounce-back walls y=0,255, "
+                               "force 1e-6 x, FP64 PDFs, two-array pull",
+                   "lattice": [n, n, n], "stencil": "D3Q19", "method": "TRT", "storage": "f64",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": head["hbm_frac"], "traffic": traffic,
+                     "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
+                     "kernel": "k_sweep<D3Q19, TRT, double>"},
+        "cpu_baseline": cpu,
+        "extras": extras,
+        "wall_s": round(time.time() - t_start, 1),
+    }
+    print(json.dumps(result))
+
+
+def bench_adjoint(torch, LBM, inputs, Timer):
+    """C4: D3Q19 SRT 128^3 channel with 5% spheres, FP32, 200 steps forward,
+    tape every 20, adjoint back to t=0 (segment recompute included)."""
+    n, T, k = 128, 200, 20
+    log("C4 D3Q19 SRT adjoint 128^3 f32, T=%d, k=%d" % (T, k))
+    mask = inputs.sphere_channel_mask(n, seed=4)
+    u0 = inputs.uniform_noise_velocity((n, n, n), 1e-3, 4, mask, dtype=np.float32)
+    lbm = LBM("D3Q19", "SRT", "f32", (n, n, n), 1 / 0.8, mask=mask, checkpoint_every=k, max_tape_steps=T)
+    lbm.set_force([1e-5, 0, 0])
+    u0t = torch.from_numpy(u0).cuda()
+    fl = torch.from_numpy(mask == 0).cuda()
+    for rep in range(2):       # first pass warms up
+        lbm.init_equilibrium(None, u0t)
+        with Timer(torch, lbm.stream) as tf:
+            lbm.step(T)
+        _, uT = lbm.macroscopic(dtype=torch.float32)
+        g = torch.zeros_like(uT)
+        g[0, :, :, -1] = 2 * uT[0, :, :, -1] * fl[:, :, -1]
+        with Timer(torch, lbm.stream) as tb:
+            lbm.adjoint_seed(g)
+            lbm.adjoint_step(T)
+            du, _, dF = lbm.adjoint_grads(dtype=torch.float32)
+    lbm.close()
+    cells = n ** 3
+    fluid = cells - int(mask.sum())
+    per_step = fluid * (2 * 19 * 4) * 2 + fluid * 3 * 19 * 4 + 3 * cells   # fwd + recompute + adjoint
+    sec = (tf.ms + tb.ms) / 1e3
+    return {"fwd_adjoint_mlups": cells * T / sec / 1e6, "forward_ms": tf.ms, "backward_ms": tb.ms,
+            "algorithmic_GBps": per_step * T / sec / 1e9, "dL_dF": [float(v) for v in dF],
+            "dL_du0_norm": float(du.double().norm())}
+
+
+def cpu_baseline(inputs):
+    """The oracle as it stands, one host thread, on a bounded sample of the
+    headline workload: a 256 x 64 x 32 slice of the channel, 10 steps."""
+    from threadpoolctl import threadpool_limits
+    from oracle import run as orun
+    dims = (256, 64, 32)
+    mask = inputs.channel_mask(*dims)
+    u = inputs.uniform_noise_velocity(dims, 1e-3, 2, mask)
+    cfg = orun.Config("D3Q19", "TRT", dict(omega=1 / 0.8, magic=3 / 16, omega_odd=0.0))
+    Ff = orun.force_field(np.array([1e-6, 0, 0]), dims)
+    with threadpool_limits(1):
+        P = orun.init_equilibrium(cfg, np.ones((32, 64, 256)), u, mask)
+        t0 = time.time()
+        steps = 10
+        P = orun.run(cfg, P, steps, mask, Ff)
+        dt = time.time() - t0
+    cells = dims[0] * dims[1] * dims[2]
+    log("CPU oracle: %.2f MLUPS (%.1f s)" % (cells * steps / dt / 1e6, dt))
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "numpy FP64 oracle, D3Q19 TRT channel 256x64x32 (same recipe as the headline), "
+                      "%d steps, %.1f s, one host thread" % (steps, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann stream-collide
+ * library.  Plain C types only: host or device pointers and sizes.
+ *
+ * Method (paper: "lbmpy: Automatic code generation for efficient parallel
+ * lattice Boltzmann methods", Bauer, Koestler, Ruede):
+ *   - lattice: DdQq velocity sets on a regular periodic grid (Sec. III-A);
+ *   - one time step = pull streaming from the upstream neighbours followed by
+ *     the local collision, fused in one kernel over two arrays
+ *     (Sec. IV-B, Fig. "stream-pull-collide");
+ *   - collision: SRT (Eq. 1), TRT (Sec. III-C), MRT in a lattice-weighted
+ *     orthogonal moment basis (Eq. 4, Sec. III-C "MRT"), cumulant (Eq. 9,
+ *     Sec. III-B); equilibrium Eq. (3) at second order, density and velocity
+ *     from Eq. (2); body force by Guo's scheme (cited in Sec. I);
+ *   - walls: halfway bounce-back of the resting-wall case of the velocity
+ *     bounce-back rule (Sec. III-C "Boundary Conditions"), compiled into the
+ *     sweep from a solid mask (Sec. IV-B "Boundary Conditions").
+ * Extensions not in the paper: PDFs stored shifted by w_q rho_0 in FP32, BF16
+ * or FP16 with FP32 collision arithmetic; a discrete adjoint sweep with a
+ * checkpoint tape.
+ *
+ * Conventions for every call
+ *   - Return value: lbm_status; LBM_OK (0) on success.  On failure nothing
+ *     has been enqueued and lbm_last_error() describes the problem.
+ *   - Arguments are validated on the host before any device work, so
+ *     argument errors never touch the GPU.
+ *   - Device pointers ("_dev") must be on the context's device.  Work is
+ *     enqueued on the stream given to lbm_create (NULL = the null stream)
+ *     and is asynchronous unless the function says "synchronises".
+ *   - Field layout: x fastest, then y, then z.  Cell index
+ *     i = (z * ny + y) * nx + x, N = nx * ny * nz.  Vector fields are
+ *     component-major: component a of cell i at [a * N + i].
+ *   - PDF layout (lbm_get_pdfs / lbm_set_pdfs): [q * N + i], unshifted FP64.
+ *     Direction order: q = 0 is the rest vector; q = 1..h are the vectors
+ *     listed below, q = h+1..2h their negatives (opposite(q) = q +/- h):
+ *       D2Q9  (h=4):  (1,0) (0,1) (1,1) (1,-1)
+ *       D3Q19 (h=9):  (1,0,0) (0,1,0) (0,0,1) (1,1,0) (1,-1,0) (1,0,1)
+ *                     (1,0,-1) (0,1,1) (0,1,-1)
+ *       D3Q27 (h=13): the D3Q19 list, then (1,1,1) (1,1,-1) (1,-1,1) (1,-1,-1)
+ *   - A context is not thread-safe.  The context owns its device memory
+ *     (PDF grids, tape, adjoint state); the caller owns every buffer it
+ *     passes in.
+ */
+#ifndef LBM_MI355X_H
+#define LBM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* stencils (Sec. III-A) */
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 };
+/* collision operators: Eq. (1); Sec. III-C TRT; Eq. (4); Eq. (9) */
+enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2, LBM_CUMULANT = 3 };
+/* PDF storage type (FP64 computes in FP64, the others in FP32); also used
+ * to describe caller field buffers (only LBM_F64 / LBM_F32 there) */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 };
+/* status codes */
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* bad argument                                  */
+  LBM_EUNSUPPORTED = -2,  /* valid request this library does not implement  */
+  LBM_ENOMEM = -3,        /* device allocation failed                      */
+  LBM_EHIP = -4,          /* a HIP runtime call failed                     */
+  LBM_ESTATE = -5,        /* call not valid in the context's current state */
+  LBM_ENONFINITE = -6     /* a reduction found NaN or Inf                  */
+};
+
+/* Relaxation rates (Sec. III-A "Relaxation rates"; runtime constants). */
+typedef struct {
+  double omega;       /* SRT omega = 1/tau; TRT even rate; MRT/cumulant shear rate */
+  double omega_bulk;  /* MRT/cumulant bulk rate (trace of the 2nd-order moments)   */
+  double omega_odd;   /* TRT odd rate; if <= 0 it is derived from `magic`          */
+  double magic;       /* TRT Lambda = (1/omega_even - 1/2)(1/omega_odd - 1/2)      */
+  double omega_hi[4]; /* MRT/cumulant rates of moment orders 3, 4, 5, 6            */
+} lbm_rates;
+
+typedef struct {
+  int32_t stencil;          /* LBM_D2Q9 | LBM_D3Q19 | LBM_D3Q27                    */
+  int32_t method;           /* LBM_SRT | LBM_TRT | LBM_MRT | LBM_CUMULANT          */
+  int32_t dtype;            /* PDF storage type                                     */
+  int32_t nx, ny, nz;       /* lattice size; nz == 1 for D2Q9; N < 2^31            */
+  lbm_rates rates;          /* every used rate must lie in (0, 2)                   */
+  double rho0;              /* reference density: storage shift and Eq. (3) rho_0  */
+  int32_t compressible;     /* 1: rho_0 = rho in Eq. (3) (default); 0: incompressible */
+  int32_t pattern;          /* 0: two-array pull (the only pattern implemented)     */
+  int32_t checkpoint_every; /* k > 0 enables the adjoint tape (PDF copy every k steps) */
+  int32_t max_tape_steps;   /* longest forward run the tape covers (adjoint only)   */
+} lbm_config;
+
+/* Supported combinations: SRT, TRT on all stencils; MRT on D2Q9 and D3Q27;
+ * CUMULANT on D2Q9 and D3Q27 with omega_hi all equal to 1, compressible and
+ * without body force.  Others return LBM_EUNSUPPORTED. */
+
+/* Create a context: validates cfg, allocates two PDF grids (plus the tape when
+ * checkpoint_every > 0) and copies the solid mask in.
+ * solid_mask_host: N bytes on the host, 1 = solid, 0 = fluid, or NULL (all
+ *   fluid, fully periodic).  Solid cells are never updated and read out as
+ *   rho = u = 0.
+ * hip_stream: a hipStream_t of the current device, or NULL.
+ * On success *out owns all allocations; release with lbm_destroy.
+ * The PDFs are initialised to rest at rho0 (shifted zero). */
+int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host,
+                   void* hip_stream, lbm_ctx** out);
+
+/* Free everything the context owns (synchronises its stream). NULL is a no-op. */
+int32_t lbm_destroy(lbm_ctx* ctx);
+
+/* Body force (Guo scheme).  F: 3 host doubles, a force constant in space; or
+ * F == NULL and profile_y = ny*3 host doubles, force (Fx, Fy, Fz) of row y at
+ * [3*y + a] (uniform in x and z).  Invalidates a recorded tape. */
+int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
+
+/* P = f^eq(rho, u) (Eq. 3) at fluid cells; resets the step counter and tape.
+ * rho_dev: N values or NULL (rho0 everywhere); u_dev: 3*N values or NULL
+ * (at rest); both of type field_dtype (LBM_F64 or LBM_F32). */
+int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
+                             int32_t field_dtype);
+
+/* Advance n >= 0 time steps (one fused stream-pull-collide launch each).
+ * With the tape enabled, the state at every multiple of k steps below
+ * max_tape_steps is copied into the tape first. */
+int32_t lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* Readout of the stored (post-collision) state: rho = sum f,
+ * u = (sum c f - F/2) / rho_0 (rho_0 = rho when compressible).
+ * rho_dev: N or NULL, u_dev: 3*N or NULL, of type field_dtype. */
+int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t field_dtype);
+
+/* FP64 totals over fluid cells: out[0] = sum rho, out[1..3] = sum of the
+ * momentum sum c f.  Synchronises.  LBM_ENONFINITE if any total is NaN/Inf
+ * (out is still written). */
+int32_t lbm_conserved(lbm_ctx* ctx, double out[4]);
+
+/* Copy the state out / in as unshifted FP64 PDFs, layout [q*N + i] in the
+ * documented direction order.  lbm_set_pdfs rounds into the storage type and
+ * resets the step counter and tape; lbm_get_pdfs synchronises. */
+int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev);
+int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
+
+/* Number of steps taken since the last init / set_pdfs. */
+int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t);
+
+/* ---- discrete adjoint (SRT, compressible, two-array pattern) ----------
+ * Forward map: P^0 = f^eq(rho_init, u_init) from lbm_init_equilibrium,
+ * P^{t+1} = collide(pull-gather(P^t)), readout as lbm_get_macroscopic.
+ * The adjoint state lambda^t = dL/dP^t runs backwards through the transposed
+ * collision Jacobian and the transposed gather (reverse streaming).
+ *
+ * Seed lambda^T from dL/drho and dL/du at the current step T (fields of type
+ * field_dtype, dL_drho_dev may be NULL).  Needs checkpoint_every > 0 and
+ * T <= max_tape_steps, else LBM_ESTATE. */
+int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_du_dev,
+                         int32_t field_dtype);
+/* Run n adjoint steps backwards (n <= steps remaining, else LBM_ESTATE);
+ * recomputes the forward states of each k-step segment from the tape. */
+int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n);
+/* Once the adjoint has reached t = 0: dL/du_init (3*N), dL/drho_init (N,
+ * or NULL) of type field_dtype, and dL/dF (3 host doubles, accumulated in
+ * FP64, or NULL).  Synchronises when dL_dF != NULL. */
+int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
+                          int32_t field_dtype, double* dL_dF);
+
+/* Bandwidth reference: copy Q planes of n elements of elem_bytes (2, 4 or 8)
+ * from src to dst with the sweep's thread layout (one thread per cell, Q
+ * loads and Q stores).  The analogue of the paper's multi-stream copy
+ * benchmark (Sec. V-A, Tab. III).  hip_stream as in lbm_create. */
+int32_t lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q,
+                   int32_t elem_bytes, void* hip_stream);
+
+/* Thread-local description of the last error. */
+const char* lbm_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_MI355X_H */

@@ -1,0 +1,307 @@
+// Discrete adjoint of the SRT + Guo + bounce-back time step.
+//
+// Forward step (the sweep): g = pull-gather(P^t) with bounce-back,
+// rho = sum g, u = (sum c g + F/2)/rho, P^{t+1} = g - omega (g - f^eq) + (1 - omega/2) S.
+// Its transpose, per fluid cell x, with lambda = lambda^{t+1}(x, .):
+//   e_q    = f^eq_q / rho = w_q (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+//   alpha  = omega sum_q lambda_q e_q
+//   beta_a = sum_q lambda_q [omega df^eq_q/du_a + dS_q/du_a]
+//          = sum_q c_qa t_q - 3 (omega rho u_a + (1 - omega/2) F_a) s0,
+//            t_q = lambda_q w_q (3 omega rho (1 + 3 c.u) + 9 (1 - omega/2) c.F),
+//            s0 = sum_q lambda_q w_q
+//   h_p    = (1 - omega) lambda_p + alpha + (c_p - u).beta / rho
+// and h_p goes back along the link it was pulled through: to slot
+// (x - c_p, p), or to (x, opp(p)) if that link was bounced.  Each slot of
+// lambda^t receives exactly one value (the gather is a permutation of fluid
+// links), so the scatter has no write conflicts.
+// dL/dF collects, per cell,
+//   sum_q lambda_q dS_q/dF_b + beta_b / (2 rho)
+//   = (1 - omega/2) [sum_q c_qb lambda_q w_q (3 + 9 c.u) - 3 u_b s0] + beta_b / (2 rho),
+// reduced per block in FP64.
+#include "sweep.h"
+
+namespace lbm {
+
+bool adjoint_supported(int stencil, int method) { return method == M_SRT && stencil >= 0 && stencil <= 2; }
+
+template <int W>
+__device__ __forceinline__ void block_sum_adj(double (&v)[W]) {
+  __shared__ double red[W][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    double s = v[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) red[c][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += red[c][i];
+      v[c] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double ld_f(const void* p, size_t i, int fdt) {
+  return fdt == 0 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+}
+__device__ __forceinline__ void st_f(void* p, size_t i, double v, int fdt) {
+  if (fdt == 0)
+    ((double*)p)[i] = v;
+  else
+    ((float*)p)[i] = (float)v;
+}
+
+// ------------------------------------------------------------------ seed
+// lambda^T_q = dL/drho + sum_a dL/du_a (c_qa - u_a)/rho with the readout
+// rho = sum P, u = (sum c P - F/2)/rho; the readout also gives dL/dF its
+// direct term -sum_x dL/du(x) / (2 rho(x)).
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                  int has_mask, const typename Storage<T>::R* __restrict__ force_y,
+                                                  const void* dL_drho, const void* dL_du, int fdt,
+                                                  typename Storage<T>::R* __restrict__ lam,
+                                                  double* __restrict__ partials, Geo g, double rho0) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  const size_t N = (size_t)g.N;
+  double dF[3] = {0, 0, 0};
+  if (c.valid) {
+    const bool solid = has_mask && (flags[c.cell] & 1);
+    if (solid) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) lam[q * N + c.cell] = R(0);
+    } else {
+      R f[L::Q];
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(P + q * N + c.cell);
+      R drho, jx, jy, jz;
+      density_momentum<L>(f, drho, jx, jy, jz);
+      const R rho = R(rho0) + drho;
+      const R inv = R(1) / rho;
+      const R ux = (jx - R(0.5) * force_y[3 * c.y]) * inv;
+      const R uy = (jy - R(0.5) * force_y[3 * c.y + 1]) * inv;
+      const R uz = (jz - R(0.5) * force_y[3 * c.y + 2]) * inv;
+      const R gx = R(ld_f(dL_du, c.cell, fdt)), gy = R(ld_f(dL_du, N + c.cell, fdt)),
+              gz = R(ld_f(dL_du, 2 * N + c.cell, fdt));
+      const R gr = dL_drho ? R(ld_f(dL_drho, c.cell, fdt)) : R(0);
+      const R base = gr - (gx * ux + gy * uy + gz * uz) * inv;
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) lam[q * N + c.cell] = base + cdot<L>(q, gx, gy, gz) * inv;
+      dF[0] = -(double)gx / (2.0 * (double)rho);
+      dF[1] = -(double)gy / (2.0 * (double)rho);
+      dF[2] = -(double)gz / (2.0 * (double)rho);
+    }
+  }
+  block_sum_adj<3>(dF);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] = dF[k];
+}
+
+// ------------------------------------------------------------------ sweep
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                   int has_mask, const typename Storage<T>::R* __restrict__ force_y,
+                                                   const typename Storage<T>::R* __restrict__ lam_in,
+                                                   typename Storage<T>::R* __restrict__ lam_out,
+                                                   double* __restrict__ partials, Geo g,
+                                                   CollideParams<typename Storage<T>::R> p) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  const size_t N = (size_t)g.N;
+  double dF[3] = {0, 0, 0};
+  int fl = 0;
+  if (c.valid && has_mask) fl = flags[c.cell];
+  if (c.valid && !(fl & 1)) {
+    R f[L::Q];
+    int up[L::Q];
+    uint32_t bb = 0;
+    gather<L, T>(P, flags, fl, c, g, f, &bb, up);
+    R lam[L::Q];
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];
+    const R F0 = force_y[3 * c.y], F1 = force_y[3 * c.y + 1], F2 = force_y[3 * c.y + 2];
+    R drho, jx, jy, jz;
+    density_momentum<L>(f, drho, jx, jy, jz);
+    const R rho = p.rho0 + drho;
+    const R inv = R(1) / rho;
+    const R ux = (jx + R(0.5) * F0) * inv, uy = (jy + R(0.5) * F1) * inv, uz = (jz + R(0.5) * F2) * inv;
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R om = p.om, fs = R(1) - R(0.5) * p.om;
+    const R omr3 = R(3) * om * rho;
+    R alpha = R(0), s0 = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const R w = R(weight<L>(q));
+      const R cu = cdot<L>(q, ux, uy, uz);
+      const R cF = cdot<L>(q, F0, F1, F2);
+      const R lw = lam[q] * w;
+      alpha += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+      s0 += lw;
+      const R t = lw * (omr3 * (R(1) + R(3) * cu) + R(9) * fs * cF);
+      const R sf = lw * (R(3) + R(9) * cu);
+      if (L::c(q, 0) == 1) { bx += t; sx += sf; }
+      if (L::c(q, 0) == -1) { bx -= t; sx -= sf; }
+      if (L::c(q, 1) == 1) { by += t; sy += sf; }
+      if (L::c(q, 1) == -1) { by -= t; sy -= sf; }
+      if (L::c(q, 2) == 1) { bz += t; sz += sf; }
+      if (L::c(q, 2) == -1) { bz -= t; sz -= sf; }
+    }
+    alpha *= om;
+    bx -= R(3) * (om * rho * ux + fs * F0) * s0;
+    by -= R(3) * (om * rho * uy + fs * F1) * s0;
+    bz -= R(3) * (om * rho * uz + fs * F2) * s0;
+    const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
+    const R one_m = R(1) - om;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const R h = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
+      const size_t dst = (bb >> q) & 1u ? (size_t)opp<L>(q) * N + c.cell : (size_t)q * N + up[q];
+      lam_out[dst] = h;
+    }
+    dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
+    dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
+    dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
+  }
+  block_sum_adj<3>(dF);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] = dF[k];
+}
+
+// ------------------------------------------------------------------ init
+// P^0 = f^eq(rho, u): dL/du_a = sum_q lambda_q w_q rho (3 c_qa + 9 (c.u) c_qa - 3 u_a),
+//                      dL/drho = sum_q lambda_q w_q (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u).
+template <class L, class R>
+__global__ __launch_bounds__(512) void k_adj_init_grad(const R* __restrict__ lam, const uint8_t* __restrict__ flags,
+                                                       int has_mask, const R* __restrict__ init_fields,
+                                                       void* dL_du0, void* dL_drho0, int fdt, Geo g) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+  double gx = 0, gy = 0, gz = 0, gr = 0;
+  if (!(has_mask && (flags[c.cell] & 1))) {
+    const R rho = init_fields[c.cell];
+    const R ux = init_fields[N + c.cell], uy = init_fields[2 * N + c.cell], uz = init_fields[3 * N + c.cell];
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    R ax = 0, ay = 0, az = 0, s0 = 0, r = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const R lw = lam[q * N + c.cell] * R(weight<L>(q));
+      const R cu = cdot<L>(q, ux, uy, uz);
+      r += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+      s0 += lw;
+      const R t = lw * (R(3) + R(9) * cu);
+      if (L::c(q, 0) == 1) ax += t;
+      if (L::c(q, 0) == -1) ax -= t;
+      if (L::c(q, 1) == 1) ay += t;
+      if (L::c(q, 1) == -1) ay -= t;
+      if (L::c(q, 2) == 1) az += t;
+      if (L::c(q, 2) == -1) az -= t;
+    }
+    gx = (double)(rho * (ax - R(3) * ux * s0));
+    gy = (double)(rho * (ay - R(3) * uy * s0));
+    gz = (double)(rho * (az - R(3) * uz * s0));
+    gr = (double)r;
+  }
+  if (dL_du0) {
+    st_f(dL_du0, c.cell, gx, fdt);
+    st_f(dL_du0, N + c.cell, gy, fdt);
+    st_f(dL_du0, 2 * N + c.cell, gz, fdt);
+  }
+  if (dL_drho0) st_f(dL_drho0, c.cell, gr, fdt);
+}
+
+template <class R>
+__global__ __launch_bounds__(512) void k_store_init_fields(const void* rho, const void* u, int fdt,
+                                                           R* __restrict__ out, Geo g, double rho0) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+  out[c.cell] = R(rho ? ld_f(rho, c.cell, fdt) : rho0);
+  for (int a = 0; a < 3; ++a) out[(a + 1) * N + c.cell] = R(u ? ld_f(u, a * N + c.cell, fdt) : 0.0);
+}
+
+// ------------------------------------------------------------------ launchers
+template <class F>
+static hipError_t by_stencil_dtype(int stencil, int dtype, F&& fn) {
+  auto by_dtype = [&](auto lat) -> hipError_t {
+    switch (dtype) {
+      case 0: return fn(lat, double());
+      case 1: return fn(lat, float());
+      case 2: return fn(lat, __bf16());
+      case 3: return fn(lat, _Float16());
+    }
+    return hipErrorInvalidValue;
+  };
+  switch (stencil) {
+    case 0: return by_dtype(D2Q9());
+    case 1: return by_dtype(D3Q19());
+    case 2: return by_dtype(D3Q27());
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                               const void* force_y, const void* dL_drho, const void* dL_du, int field_dtype,
+                               void* lam, double* partials, const Geo& g, const Params& p, hipStream_t s) {
+  return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
+    using L = decltype(lat);
+    using T = decltype(tag);
+    using R = typename Storage<T>::R;
+    hipLaunchKernelGGL((k_adj_seed<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                       has_mask, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam, partials, g, p.rho0);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_adjoint_sweep(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                                const void* force_y, const void* lam_in, void* lam_out, double* partials,
+                                const Geo& g, const Params& p, hipStream_t s) {
+  return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
+    using L = decltype(lat);
+    using T = decltype(tag);
+    using R = typename Storage<T>::R;
+    const CollideParams<R> cp = to_collide_params<R>(p);
+    hipLaunchKernelGGL((k_adj_sweep<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                       has_mask, (const R*)force_y, (const R*)lam_in, (R*)lam_out, partials, g, cp);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags, int has_mask,
+                                    const void* init_fields, void* dL_du0, void* dL_drho0, int field_dtype,
+                                    const Geo& g, const Params& p, hipStream_t s) {
+  (void)p;
+  auto run = [&](auto lat, auto rtag) -> hipError_t {
+    using L = decltype(lat);
+    using R = decltype(rtag);
+    hipLaunchKernelGGL((k_adj_init_grad<L, R>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const R*)lam,
+                       flags, has_mask, (const R*)init_fields, dL_du0, dL_drho0, field_dtype, g);
+    return hipGetLastError();
+  };
+  const bool dbl = dtype == 0;
+  switch (stencil) {
+    case 0: return dbl ? run(D2Q9(), double()) : run(D2Q9(), float());
+    case 1: return dbl ? run(D3Q19(), double()) : run(D3Q19(), float());
+    case 2: return dbl ? run(D3Q27(), double()) : run(D3Q27(), float());
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_store_init_fields(int dtype, const void* rho, const void* u, int field_dtype, void* init_fields,
+                                    const Geo& g, const Params& p, hipStream_t s) {
+  if (dtype == 0) {
+    hipLaunchKernelGGL((k_store_init_fields<double>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, rho, u,
+                       field_dtype, (double*)init_fields, g, p.rho0);
+  } else {
+    hipLaunchKernelGGL((k_store_init_fields<float>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, rho, u,
+                       field_dtype, (float*)init_fields, g, p.rho0);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm

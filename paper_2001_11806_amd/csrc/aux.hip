@@ -1,0 +1,376 @@
+// Per-cell kernels around the sweep: flag building, initialisation,
+// macroscopic readout, FP64 conservation totals, PDF import/export, the
+// Q-stream copy bandwidth reference, and small reduction helpers.
+//
+// These run once per run or once per readout, not per time step, so they
+// compute in FP64 regardless of the storage type.
+#include "sweep.h"
+
+namespace lbm {
+
+// --------------------------------------------------------------- dispatch
+bool sweep_supported(int stencil, int method) {
+  if (method == M_SRT || method == M_TRT) return stencil >= 0 && stencil <= 2;
+  if (method == M_MRT || method == M_CUMULANT) return stencil == 0 || stencil == 2;
+  return false;
+}
+
+hipError_t launch_sweep(int stencil, int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+                        const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s) {
+  switch (stencil) {
+    case 0: return launch_sweep_d2q9(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
+    case 1: return launch_sweep_d3q19(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
+    case 2: return launch_sweep_d3q27(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define LBM_STENCIL_SWITCH(stencil, CALL) \
+  switch (stencil) {                      \
+    case 0: { using L = D2Q9; CALL; }     \
+    case 1: { using L = D3Q19; CALL; }    \
+    case 2: { using L = D3Q27; CALL; }    \
+  }                                       \
+  return hipErrorInvalidValue;
+
+#define LBM_DTYPE_SWITCH(dtype, CALL)          \
+  switch (dtype) {                             \
+    case 0: { using T = double; CALL; }        \
+    case 1: { using T = float; CALL; }         \
+    case 2: { using T = __bf16; CALL; }        \
+    case 3: { using T = _Float16; CALL; }      \
+  }                                            \
+  return hipErrorInvalidValue;
+
+template <class FT>
+__device__ __forceinline__ double ld_field(const void* p, size_t i) {
+  return (double)((const FT*)p)[i];
+}
+
+__device__ __forceinline__ double ld_any(const void* p, size_t i, int field_dtype) {
+  return field_dtype == 0 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+}
+
+__device__ __forceinline__ void st_any(void* p, size_t i, double v, int field_dtype) {
+  if (field_dtype == 0)
+    ((double*)p)[i] = v;
+  else
+    ((float*)p)[i] = (float)v;
+}
+
+template <class T>
+__device__ __forceinline__ void store_from_double(T* p, double v) {
+  *p = static_cast<T>(v);
+}
+
+// Block-wide sum of `v` for every component; result valid in thread 0.
+template <int W>
+__device__ __forceinline__ void block_sum(double (&v)[W]) {
+  __shared__ double red[W][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    double s = v[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) red[c][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += red[c][i];
+      v[c] = s;
+    }
+  }
+}
+
+// --------------------------------------------------------------- flags
+// bit 0: solid; bit 1: fluid cell with at least one solid upstream neighbour.
+template <class L>
+__global__ __launch_bounds__(512) void k_build_flags(const uint8_t* __restrict__ solid, uint8_t* __restrict__ flags,
+                                                     Geo g) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  LBM_NEIGHBOURS(c, g)
+  uint8_t f = solid[c.cell] ? 1 : 0;
+  if (!f) {
+    bool near = false;
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) near |= solid[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] != 0;
+    if (near) f |= 2;
+  }
+  flags[c.cell] = f;
+}
+
+hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, const Geo& g, hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    hipLaunchKernelGGL(k_build_flags<L>, dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, solid, flags, g);
+    return hipGetLastError();
+  })
+}
+
+// --------------------------------------------------------------- init
+// P = f^eq(rho, u) (Eq. 3, second order), stored shifted by w rho_0.
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_init(T* __restrict__ P, const uint8_t* __restrict__ flags, int has_mask,
+                                              const void* rho, const void* u, int fdt, Geo g, double rho0,
+                                              int compressible) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+  const bool solid = has_mask && (flags[c.cell] & 1);
+  const double r = rho ? ld_any(rho, c.cell, fdt) : rho0;
+  double ux = 0, uy = 0, uz = 0;
+  if (u) {
+    ux = ld_any(u, c.cell, fdt);
+    uy = ld_any(u, N + c.cell, fdt);
+    uz = ld_any(u, 2 * N + c.cell, fdt);
+  }
+  const double rr = compressible ? r : rho0;
+  const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    double v = 0.0;
+    if (!solid) {
+      const double cu = cdot<L>(q, ux, uy, uz);
+      v = weight<L>(q) * ((r - rho0) + rr * (3.0 * cu + 4.5 * cu * cu - usq));
+    }
+    store_from_double(P + q * N + c.cell, v);
+  }
+}
+
+hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, const void* rho,
+                       const void* u, int field_dtype, const Geo& g, const Params& p, hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    LBM_DTYPE_SWITCH(dtype, {
+      hipLaunchKernelGGL((k_init<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags, has_mask,
+                         rho, u, field_dtype, g, p.rho0, p.compressible);
+      return hipGetLastError();
+    })
+  })
+}
+
+// --------------------------------------------------------------- readout
+// Stored state is post-collision: rho = sum f, u = (sum c f - F/2) / rho_0.
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                 int has_mask, const typename Storage<T>::R* __restrict__ force_y,
+                                                 void* rho_out, void* u_out, int fdt, Geo g, double rho0,
+                                                 int compressible) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+  double r = 0, ux = 0, uy = 0, uz = 0;
+  if (!(has_mask && (flags[c.cell] & 1))) {
+    double d = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const double v = (double)Storage<T>::load(P + q * N + c.cell);
+      d += v;
+      jx += L::c(q, 0) * v;
+      jy += L::c(q, 1) * v;
+      jz += L::c(q, 2) * v;
+    }
+    r = rho0 + d;
+    const double inv = 1.0 / (compressible ? r : rho0);
+    ux = (jx - 0.5 * (double)force_y[3 * c.y]) * inv;
+    uy = (jy - 0.5 * (double)force_y[3 * c.y + 1]) * inv;
+    uz = (jz - 0.5 * (double)force_y[3 * c.y + 2]) * inv;
+  }
+  if (rho_out) st_any(rho_out, c.cell, r, fdt);
+  if (u_out) {
+    st_any(u_out, c.cell, ux, fdt);
+    st_any(u_out, N + c.cell, uy, fdt);
+    st_any(u_out, 2 * N + c.cell, uz, fdt);
+  }
+}
+
+hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                          const void* force_y, void* rho, void* u, int field_dtype, const Geo& g, const Params& p,
+                          hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    LBM_DTYPE_SWITCH(dtype, {
+      using R = typename Storage<T>::R;
+      hipLaunchKernelGGL((k_readout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                         has_mask, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible);
+      return hipGetLastError();
+    })
+  })
+}
+
+// --------------------------------------------------------------- totals
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_conserved(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                   int has_mask, double* __restrict__ partials, Geo g,
+                                                   double rho0) {
+  const CellIdx c = cell_of(g);
+  const size_t N = (size_t)g.N;
+  double v[4] = {0, 0, 0, 0};
+  if (c.valid && !(has_mask && (flags[c.cell] & 1))) {
+    double d = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const double f = (double)Storage<T>::load(P + q * N + c.cell);
+      d += f;
+      v[1] += L::c(q, 0) * f;
+      v[2] += L::c(q, 1) * f;
+      v[3] += L::c(q, 2) * f;
+    }
+    v[0] = rho0 + d;
+  }
+  block_sum<4>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partials[(size_t)blockIdx.x * 4 + k] = v[k];
+}
+
+// Single-block reduction of nparts rows of `width` doubles into acc.
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partials, int64_t nparts,
+                                                      int width, double* __restrict__ acc, int accumulate) {
+  for (int k = 0; k < width; ++k) {
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) v[0] += partials[i * width + k];
+    block_sum<1>(v);
+    if (threadIdx.x == 0) acc[k] = accumulate ? acc[k] + v[0] : v[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc, int accumulate,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nparts, width, acc, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                            double* partials, double* out4, const Geo& g, const Params& p, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  auto body = [&](auto lat, auto tag) -> hipError_t {
+    using L = decltype(lat);
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_conserved<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                       has_mask, partials, g, p.rho0);
+    return hipGetLastError();
+  };
+  auto by_dtype = [&](auto lat) -> hipError_t {
+    switch (dtype) {
+      case 0: return body(lat, double());
+      case 1: return body(lat, float());
+      case 2: return body(lat, __bf16());
+      case 3: return body(lat, _Float16());
+    }
+    return hipErrorInvalidValue;
+  };
+  switch (stencil) {
+    case 0: e = by_dtype(D2Q9()); break;
+    case 1: e = by_dtype(D3Q19()); break;
+    case 2: e = by_dtype(D3Q27()); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return launch_sum_partials(partials, num_blocks(g), 4, out4, 0, s);
+}
+
+// --------------------------------------------------------------- PDF I/O
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, double* __restrict__ out, Geo g,
+                                                  double rho0) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    out[q * N + c.cell] = (double)Storage<T>::load(P + q * N + c.cell) + weight<L>(q) * rho0;
+}
+
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_set_pdfs(T* __restrict__ P, const double* __restrict__ in, Geo g,
+                                                  double rho0) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, in[q * N + c.cell] - weight<L>(q) * rho0);
+}
+
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, double* out, const Geo& g, const Params& p,
+                           hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    LBM_DTYPE_SWITCH(dtype, {
+      hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, out, g,
+                         p.rho0);
+      return hipGetLastError();
+    })
+  })
+}
+
+hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const double* in, const Geo& g, const Params& p,
+                           hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    LBM_DTYPE_SWITCH(dtype, {
+      hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, in, g,
+                         p.rho0);
+      return hipGetLastError();
+    })
+  })
+}
+
+// --------------------------------------------------------------- copy-Q
+// Bandwidth reference: same thread layout and access pattern as the sweep
+// (all Q loads, then all Q stores), without the gather offsets or arithmetic.
+template <class E, int Q>
+__global__ __launch_bounds__(256) void k_copy_q(const E* __restrict__ src, E* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  E v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = src[q * n + i];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) dst[q * n + i] = v[q];
+}
+
+template <class E>
+__global__ __launch_bounds__(256) void k_copy_generic(const E* __restrict__ src, E* __restrict__ dst, int64_t n,
+                                                      int Q) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int q = 0; q < Q; ++q) dst[q * n + i] = src[q * n + i];
+}
+
+template <class E>
+hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (q) {
+    case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
+    case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
+    case 27: hipLaunchKernelGGL((k_copy_q<E, 27>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
+    default: hipLaunchKernelGGL((k_copy_generic<E>), grid, block, 0, s, (const E*)src, (E*)dst, n, q);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, hipStream_t s) {
+  switch (elem_bytes) {
+    case 2: return copy_q_typed<uint16_t>(src, dst, n, q, s);
+    case 4: return copy_q_typed<uint32_t>(src, dst, n, q, s);
+    case 8: return copy_q_typed<uint64_t>(src, dst, n, q, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------- zero fill
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
+  const int64_t words = bytes / 4;  // every buffer here is a multiple of 4 bytes
+  int64_t blocks = (words + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,434 @@
+// Per-cell collision operators on shifted populations.
+//
+// Input/output f[q] holds the shifted population f_q - w_q rho_0 in the
+// compute type R.  All operators work on these small deviations directly:
+// density deviation drho = sum f, momentum j = sum c f (the shift has zero
+// momentum), so no large cancelling sums are ever formed in FP32.
+//
+// Guo forcing (cited by the paper, Sec. I): velocity u = (j + F/2)/rho_0,
+// source S_q = w_q [3 (c_q - u).F + 9 (c_q.u)(c_q.F)] (c_s^2 = 1/3) with the
+// (1 - omega/2) prefactor of each relaxation group.
+#pragma once
+
+#include "lattice.h"
+
+namespace lbm {
+
+enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3 };
+
+template <class R>
+struct CollideParams {
+  R rho0;
+  R om;       // SRT omega / TRT even / MRT, cumulant shear
+  R om_b;     // bulk
+  R om_o;     // TRT odd
+  R hi[4];    // orders 3..6
+  int compressible;
+};
+
+// c_q . (x, y, z) with the constant components folded away.
+template <class L, class R>
+__device__ __forceinline__ R cdot(int q, R x, R y, R z) {
+  R s = R(0);
+  if (L::c(q, 0) == 1) s += x;
+  if (L::c(q, 0) == -1) s -= x;
+  if (L::c(q, 1) == 1) s += y;
+  if (L::c(q, 1) == -1) s -= y;
+  if (L::c(q, 2) == 1) s += z;
+  if (L::c(q, 2) == -1) s -= z;
+  return s;
+}
+
+template <class L, class R>
+__device__ __forceinline__ void density_momentum(const R* f, R& drho, R& jx, R& jy, R& jz) {
+  drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    drho += f[q];
+    if (L::c(q, 0) == 1) jx += f[q];
+    if (L::c(q, 0) == -1) jx -= f[q];
+    if (L::c(q, 1) == 1) jy += f[q];
+    if (L::c(q, 1) == -1) jy -= f[q];
+    if (L::c(q, 2) == 1) jz += f[q];
+    if (L::c(q, 2) == -1) jz -= f[q];
+  }
+}
+
+// ---------------------------------------------------------------- SRT
+// Eq. (1): f* = f - omega (f - f^eq) + (1 - omega/2) S, f^eq from Eq. (3).
+template <class L, class R>
+__device__ __forceinline__ void collide_srt(R* f, const R* F, const CollideParams<R>& p) {
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (jx + R(0.5) * F[0]) * inv, uy = (jy + R(0.5) * F[1]) * inv,
+          uz = (jz + R(0.5) * F[2]) * inv;
+  const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF3 = R(3) * (ux * F[0] + uy * F[1] + uz * F[2]);
+  const R om = p.om, fs = R(1) - R(0.5) * p.om;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R w = R(weight<L>(q));
+    const R cu = cdot<L>(q, ux, uy, uz);
+    const R cF = cdot<L>(q, F[0], F[1], F[2]);
+    const R feq = w * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));
+    const R S = w * (R(3) * cF - uF3 + R(9) * cu * cF);
+    f[q] = f[q] - om * (f[q] - feq) + fs * S;
+  }
+}
+
+// ---------------------------------------------------------------- TRT
+// Even moments relax with omega_e, odd with omega_o (Sec. III-C); written on
+// the symmetric / antisymmetric parts of each (q, opp(q)) pair, where even
+// moments vanish on the antisymmetric and odd moments on the symmetric part.
+template <class L, class R>
+__device__ __forceinline__ void collide_trt(R* f, const R* F, const CollideParams<R>& p) {
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (jx + R(0.5) * F[0]) * inv, uy = (jy + R(0.5) * F[1]) * inv,
+          uz = (jz + R(0.5) * F[2]) * inv;
+  const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF3 = R(3) * (ux * F[0] + uy * F[1] + uz * F[2]);
+  const R we = p.om, wo = p.om_o;
+  const R fe = R(1) - R(0.5) * we, fo = R(1) - R(0.5) * wo;
+  {
+    const R w = R(weight<L>(0));
+    const R feq = w * (drho - rr * usq);
+    f[0] = f[0] - we * (f[0] - feq) - fe * w * uF3;
+  }
+#pragma unroll
+  for (int q = 1; q <= L::H; ++q) {
+    const int o = q + L::H;
+    const R w = R(weight<L>(q));
+    const R cu = cdot<L>(q, ux, uy, uz);
+    const R cF = cdot<L>(q, F[0], F[1], F[2]);
+    const R fp = R(0.5) * (f[q] + f[o]), fm = R(0.5) * (f[q] - f[o]);
+    const R ep = w * (drho + rr * (R(4.5) * cu * cu - usq));
+    const R em = w * rr * R(3) * cu;
+    const R sp = w * (R(9) * cu * cF - uF3);
+    const R sm = w * R(3) * cF;
+    const R dp = -we * (fp - ep) + fe * sp;
+    const R dm = -wo * (fm - em) + fo * sm;
+    f[q] += dp + dm;
+    f[o] += dp - dm;
+  }
+}
+
+// ---------------------------------------------------------------- MRT
+// Eq. (4) in the lattice-weighted orthogonal basis built by the paper's
+// Gram-Schmidt procedure.  On the tensor-product stencils D2Q9 / D3Q27 that
+// basis spans, group by group, the same subspaces as the products
+// p_a(c_x) p_b(c_y) p_c(c_z) of the 1-D weighted-orthogonal polynomials
+// p_0 = 1, p_1 = c, p_2 = 3c^2 - 1 (norms 1, 1/3, 2), and the relaxation
+// depends only on those subspaces.  So the moment transform factorises into
+// three 1-D 3-point transforms per axis, forward and back:
+//   A_k = sum_q H_k(c_q) f_q,    f*_q = f_q + w_q sum_k H_k(c_q) gamma_k,
+//   gamma_k = -omega_g (A_k - A_k^eq) / |H_k|^2 + (1 - omega_g/2) sigma_k,
+// where sigma_k are the coefficients of the Guo source in the same basis.
+// Groups: order 0, 1 conserved; order 2 split into shear (off-diagonal and
+// traceless diagonal, omega) and bulk (trace, omega_b); order n >= 3 hi[n-3].
+// Eq. (3) has no component of order >= 3 on these stencils.
+template <class L, class R>
+__device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
+  R a[3][3][NK];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) a[i][j][k] = f[qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0)];
+  // forward 1-D transforms: (v-, v0, v+) -> (sum, v+ - v-, 2v- - v0 + 2v+)
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const R m = a[0][j][k], z = a[1][j][k], pp = a[2][j][k];
+      a[0][j][k] = m + z + pp;
+      a[1][j][k] = pp - m;
+      a[2][j][k] = R(2) * (m + pp) - z;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const R m = a[i][0][k], z = a[i][1][k], pp = a[i][2][k];
+      a[i][0][k] = m + z + pp;
+      a[i][1][k] = pp - m;
+      a[i][2][k] = R(2) * (m + pp) - z;
+    }
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R m = a[i][j][0], z = a[i][j][NK > 1 ? 1 : 0], pp = a[i][j][NK - 1];
+        a[i][j][0] = m + z + pp;
+        a[i][j][NK > 1 ? 1 : 0] = pp - m;
+        a[i][j][NK - 1] = R(2) * (m + pp) - z;
+      }
+  }
+  // a[i][j][k] now holds A for Hermite orders (i, j, k) (k = 0 in 2-D)
+  const R drho = a[0][0][0];
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (a[1][0][0] + R(0.5) * F[0]) * inv;
+  const R uy = (a[0][1][0] + R(0.5) * F[1]) * inv;
+  const R uz = (D == 3) ? (a[0][0][NK > 1 ? 1 : 0] + R(0.5) * F[2]) * inv : R(0);
+  const R om = p.om, omb = p.om_b;
+  const R fs = R(1) - R(0.5) * om, fb = R(1) - R(0.5) * omb;
+  // gamma in place
+  // order 0 and 1: conserved (rate 0); the source gives sigma = 3 F_a
+  a[0][0][0] = R(0);
+  a[1][0][0] = R(3) * F[0];
+  a[0][1][0] = R(3) * F[1];
+  if constexpr (D == 3) a[0][0][1] = R(3) * F[2];
+  // order 2, off-diagonal: |H|^2 = 1/9, A^eq = rr u_a u_b, sigma = 9 (u_a F_b + u_b F_a)
+  {
+    a[1][1][0] = -om * R(9) * (a[1][1][0] - rr * ux * uy) + fs * R(9) * (ux * F[1] + uy * F[0]);
+    if constexpr (D == 3) {
+      a[1][0][1] = -om * R(9) * (a[1][0][1] - rr * ux * uz) + fs * R(9) * (ux * F[2] + uz * F[0]);
+      a[0][1][1] = -om * R(9) * (a[0][1][1] - rr * uy * uz) + fs * R(9) * (uy * F[2] + uz * F[1]);
+    }
+  }
+  // order 2, diagonal: |H|^2 = 2, A^eq = 3 rr u_a^2, sigma = 3 u_a F_a;
+  // trace part relaxes with omega_b, traceless part with omega
+  {
+    R An[3], sg[3];
+    An[0] = a[2][0][0] - R(3) * rr * ux * ux;
+    An[1] = a[0][2][0] - R(3) * rr * uy * uy;
+    An[2] = (D == 3) ? a[0][0][NK - 1] - R(3) * rr * uz * uz : R(0);
+    sg[0] = R(3) * ux * F[0];
+    sg[1] = R(3) * uy * F[1];
+    sg[2] = R(3) * uz * F[2];
+    const R invD = R(1) / R(D);
+    const R mA = (An[0] + An[1] + An[2]) * invD;
+    const R mS = (sg[0] + sg[1] + sg[2]) * invD;
+    R g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      g[c] = -R(0.5) * (om * (An[c] - mA) + omb * mA) + fs * (sg[c] - mS) + fb * mS;
+    a[2][0][0] = g[0];
+    a[0][2][0] = g[1];
+    if constexpr (D == 3) a[0][0][NK - 1] = g[2];
+  }
+  // orders >= 3: A^eq = 0, no source
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int kk = (D == 3) ? k : 0;
+        const int n = i + j + kk;
+        if (n >= 3) {
+          const R invn = R((i == 1 ? 3.0 : (i == 2 ? 0.5 : 1.0)) * (j == 1 ? 3.0 : (j == 2 ? 0.5 : 1.0)) *
+                           (kk == 1 ? 3.0 : (kk == 2 ? 0.5 : 1.0)));
+          a[i][j][k] = -p.hi[n - 3] * invn * a[i][j][k];
+        }
+      }
+  // back transforms with the 1-D weights (1/6, 2/3, 1/6):
+  // (g0, g1, g2) -> w(-1)(g0 - g1 + 2g2), w(0)(g0 - g2), w(+1)(g0 + g1 + 2g2)
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R g0 = a[i][j][0], g1 = a[i][j][NK > 1 ? 1 : 0], g2 = a[i][j][NK - 1];
+        a[i][j][0] = R(1.0 / 6.0) * (g0 - g1 + R(2) * g2);
+        a[i][j][NK > 1 ? 1 : 0] = R(2.0 / 3.0) * (g0 - g2);
+        a[i][j][NK - 1] = R(1.0 / 6.0) * (g0 + g1 + R(2) * g2);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const R g0 = a[i][0][k], g1 = a[i][1][k], g2 = a[i][2][k];
+      a[i][0][k] = R(1.0 / 6.0) * (g0 - g1 + R(2) * g2);
+      a[i][1][k] = R(2.0 / 3.0) * (g0 - g2);
+      a[i][2][k] = R(1.0 / 6.0) * (g0 + g1 + R(2) * g2);
+    }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const R g0 = a[0][j][k], g1 = a[1][j][k], g2 = a[2][j][k];
+      a[0][j][k] = R(1.0 / 6.0) * (g0 - g1 + R(2) * g2);
+      a[1][j][k] = R(2.0 / 3.0) * (g0 - g2);
+      a[2][j][k] = R(1.0 / 6.0) * (g0 + g1 + R(2) * g2);
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
+        f[q] += a[i][j][k];
+      }
+}
+
+// ---------------------------------------------------------------- cumulant
+// Cumulant collision (Eq. 9, Sec. III-B) for the case where every rate of
+// order >= 3 is 1.  Then all post-collision cumulants of order >= 3 vanish:
+// the post-collision state is the discrete distribution whose cumulant
+// generating function is quadratic, ln rho + u.xi + xi^T K* xi / 2, i.e. its
+// central moments are Gaussian (Isserlis): c_200 = K_xx,
+// c_220 = K_xx K_yy + 2 K_xy^2, c_211 = K_xx K_yz + 2 K_xy K_xz, c_222 = ...,
+// all odd ones zero.  Moments with exponents <= 2 per axis map back to
+// populations by a per-axis 3-point transform (central -> raw -> f).
+// Second-order cumulants: K = Pi/rho - u u^T; shear part (off-diagonal and
+// traceless diagonal) relaxes with omega, the trace with omega_b, towards the
+// Maxwellian value c_s^2 I.
+// Numerically, K* = c_s^2 I + Dv and the result is assembled as
+//   f*_q - w_q rho_0 = drho prod phi + rho_0 (prod phi - prod w) + rho T_u[dc]
+// with the factorised equilibrium phi_a(c) (the Gaussian for Dv = 0) and dc
+// the central-moment deviations caused by Dv, so only small quantities are
+// formed in FP32.
+template <class L, class R>
+__device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr R cs2 = R(1.0 / 3.0);
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  R Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    if (cx != 0) Pxx += f[q];
+    if (cy != 0) Pyy += f[q];
+    if (cz != 0) Pzz += f[q];
+    if (cx * cy == 1) Pxy += f[q];
+    if (cx * cy == -1) Pxy -= f[q];
+    if (cx * cz == 1) Pxz += f[q];
+    if (cx * cz == -1) Pxz -= f[q];
+    if (cy * cz == 1) Pyz += f[q];
+    if (cy * cz == -1) Pyz -= f[q];
+  }
+  const R rho = p.rho0 + drho;
+  const R inv = R(1) / rho;
+  const R u[3] = {jx * inv, jy * inv, jz * inv};
+  // non-equilibrium second cumulants (shift: sum c_a c_b w rho_0 = c_s^2 rho_0 delta)
+  const R Kxx = (Pxx - drho * cs2) * inv - u[0] * u[0];
+  const R Kyy = (Pyy - drho * cs2) * inv - u[1] * u[1];
+  const R Kzz = (D == 3) ? (Pzz - drho * cs2) * inv - u[2] * u[2] : R(0);
+  const R tr = (Kxx + Kyy + Kzz) * (R(1) / R(D));
+  const R ks = R(1) - p.om, kb = R(1) - p.om_b;
+  const R Dxx = ks * (Kxx - tr) + kb * tr;
+  const R Dyy = ks * (Kyy - tr) + kb * tr;
+  const R Dzz = (D == 3) ? ks * (Kzz - tr) + kb * tr : R(0);
+  const R Dxy = ks * (Pxy * inv - u[0] * u[1]);
+  const R Dxz = (D == 3) ? ks * (Pxz * inv - u[0] * u[2]) : R(0);
+  const R Dyz = (D == 3) ? ks * (Pyz * inv - u[1] * u[2]) : R(0);
+  // central-moment deviations dc[a][b][c]
+  constexpr int NK = (D == 3) ? 3 : 1;
+  R c[3][3][NK];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) c[i][j][k] = R(0);
+  c[2][0][0] = Dxx;
+  c[0][2][0] = Dyy;
+  c[1][1][0] = Dxy;
+  c[2][2][0] = cs2 * (Dxx + Dyy) + Dxx * Dyy + R(2) * Dxy * Dxy;
+  if constexpr (D == 3) {
+    c[0][0][NK - 1] = Dzz;
+    c[1][0][NK > 1 ? 1 : 0] = Dxz;
+    c[0][1][NK > 1 ? 1 : 0] = Dyz;
+    c[2][0][NK - 1] = cs2 * (Dxx + Dzz) + Dxx * Dzz + R(2) * Dxz * Dxz;
+    c[0][2][NK - 1] = cs2 * (Dyy + Dzz) + Dyy * Dzz + R(2) * Dyz * Dyz;
+    c[2][1][NK > 1 ? 1 : 0] = (cs2 + Dxx) * Dyz + R(2) * Dxy * Dxz;
+    c[1][2][NK > 1 ? 1 : 0] = (cs2 + Dyy) * Dxz + R(2) * Dxy * Dyz;
+    c[1][1][NK - 1] = (cs2 + Dzz) * Dxy + R(2) * Dxz * Dyz;
+    c[2][2][NK - 1] = cs2 * cs2 * (Dxx + Dyy + Dzz) + cs2 * (Dxx * Dyy + Dxx * Dzz + Dyy * Dzz) +
+                      Dxx * Dyy * Dzz + R(2) * (cs2 + Dxx) * Dyz * Dyz + R(2) * (cs2 + Dyy) * Dxz * Dxz +
+                      R(2) * (cs2 + Dzz) * Dxy * Dxy + R(8) * Dxy * Dxz * Dyz;
+  }
+  // per-axis central -> population transform with mean u_a:
+  // f(0) = k0 (1 - u^2) - 2u k1 - k2, f(+-1) = (k0 (u^2 +- u) + k1 (2u +- 1) + k2) / 2
+  if constexpr (D == 3) {
+    const R v = u[2], v2 = v * v;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R k0 = c[i][j][0], k1 = c[i][j][NK > 1 ? 1 : 0], k2 = c[i][j][NK - 1];
+        c[i][j][0] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
+        c[i][j][NK > 1 ? 1 : 0] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
+        c[i][j][NK - 1] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
+      }
+  }
+  {
+    const R v = u[1], v2 = v * v;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const R k0 = c[i][0][k], k1 = c[i][1][k], k2 = c[i][2][k];
+        c[i][0][k] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
+        c[i][1][k] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
+        c[i][2][k] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
+      }
+  }
+  {
+    const R v = u[0], v2 = v * v;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const R k0 = c[0][j][k], k1 = c[1][j][k], k2 = c[2][j][k];
+        c[0][j][k] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
+        c[1][j][k] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
+        c[2][j][k] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
+      }
+  }
+  // factorised equilibrium phi = w1 + dphi per axis
+  R w1[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  R ph[3][3], dph[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R v = u[a], v2 = v * v;
+    dph[a][0] = R(0.5) * (v2 - v);
+    dph[a][1] = -v2;
+    dph[a][2] = R(0.5) * (v2 + v);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) ph[a][s] = w1[s] + dph[a][s];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
+        R prod, dprod;
+        if constexpr (D == 3) {
+          prod = ph[0][i] * ph[1][j] * ph[2][k];
+          dprod = dph[0][i] * ph[1][j] * ph[2][k] + w1[i] * dph[1][j] * ph[2][k] + w1[i] * w1[j] * dph[2][k];
+        } else {
+          prod = ph[0][i] * ph[1][j];
+          dprod = dph[0][i] * ph[1][j] + w1[i] * dph[1][j];
+        }
+        f[q] = drho * prod + p.rho0 * dprod + rho * c[i][j][k];
+      }
+}
+
+template <class L, int M, class R>
+__device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>& p) {
+  if constexpr (M == M_SRT) collide_srt<L>(f, F, p);
+  else if constexpr (M == M_TRT) collide_trt<L>(f, F, p);
+  else if constexpr (M == M_MRT) collide_mrt<L>(f, F, p);
+  else collide_cumulant<L>(f, F, p);
+}
+
+}  // namespace lbm

@@ -1,0 +1,76 @@
+// Host-side launch interface between the runtime (runtime.hip) and the
+// kernels (sweep.hip, aux.hip, adjoint.hip).  Every launcher enqueues on the
+// given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Geometry of one launch: one thread per cell, each block covers one
+// contiguous x-segment of one (y, z) row; nxb segments per row.
+struct Geo {
+  int nx, ny, nz;
+  int nxb;        // x-segments per row
+  int bx;         // threads per block (multiple of 64)
+  int64_t N;      // nx * ny * nz
+};
+
+// Runtime parameters in FP64; each launcher converts to its compute type.
+struct Params {
+  double rho0;
+  double om, om_b, om_o;
+  double hi[4];
+  int compressible;
+};
+
+inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
+
+// forward
+hipError_t launch_sweep(int stencil, int method, int dtype, const void* src, void* dst,
+                        const uint8_t* flags, const void* force_y, const Geo& g, const Params& p,
+                        int has_mask, hipStream_t s);
+bool sweep_supported(int stencil, int method);
+
+// auxiliary (aux.hip)
+hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, const Geo& g,
+                              hipStream_t s);
+hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask,
+                       const void* rho, const void* u, int field_dtype, const Geo& g,
+                       const Params& p, hipStream_t s);
+hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                          const void* force_y, void* rho, void* u, int field_dtype, const Geo& g,
+                          const Params& p, hipStream_t s);
+hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags,
+                            int has_mask, double* partials, double* out4, const Geo& g,
+                            const Params& p, hipStream_t s);
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, double* out, const Geo& g,
+                           const Params& p, hipStream_t s);
+hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const double* in, const Geo& g,
+                           const Params& p, hipStream_t s);
+hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes,
+                         hipStream_t s);
+hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc,
+                               int accumulate, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+
+// adjoint (adjoint.hip)
+bool adjoint_supported(int stencil, int method);
+hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags,
+                               int has_mask, const void* force_y, const void* dL_drho,
+                               const void* dL_du, int field_dtype, void* lam, double* partials,
+                               const Geo& g, const Params& p, hipStream_t s);
+hipError_t launch_adjoint_sweep(int stencil, int dtype, const void* P, const uint8_t* flags,
+                                int has_mask, const void* force_y, const void* lam_in,
+                                void* lam_out, double* partials, const Geo& g, const Params& p,
+                                hipStream_t s);
+hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags,
+                                    int has_mask, const void* init_fields, void* dL_du0,
+                                    void* dL_drho0, int field_dtype, const Geo& g,
+                                    const Params& p, hipStream_t s);
+hipError_t launch_store_init_fields(int dtype, const void* rho, const void* u, int field_dtype,
+                                   void* init_fields, const Geo& g, const Params& p,
+                                   hipStream_t s);
+
+}  // namespace lbm

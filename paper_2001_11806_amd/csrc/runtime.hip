@@ -1,0 +1,496 @@
+// Host runtime behind the C ABI of include/lbm.h: argument validation,
+// device buffers, the step loop, the checkpoint tape and the adjoint driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int q_of(int stencil) { return stencil == LBM_D2Q9 ? 9 : (stencil == LBM_D3Q19 ? 19 : 27); }
+size_t storage_bytes(int dtype) { return dtype == LBM_F64 ? 8 : (dtype == LBM_F32 ? 4 : 2); }
+size_t compute_bytes(int dtype) { return dtype == LBM_F64 ? 8 : 4; }
+bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_config cfg{};
+  int Q = 0;
+  Geo g{};
+  Params p{};
+  hipStream_t stream = nullptr;
+  size_t grid_bytes = 0;
+  void* grid[2] = {nullptr, nullptr};
+  int cur = 0;
+  uint8_t* flags = nullptr;
+  int has_mask = 0;
+  void* force = nullptr;       // compute type, 3 * ny
+  double* partials = nullptr;  // 4 doubles per block
+  double* acc = nullptr;       // [0..2] adjoint dL/dF, [4..7] conservation totals
+  int64_t t = 0;
+  // tape
+  int k = 0;
+  int nslots = 0;
+  void* tape = nullptr;        // nslots grids: P^0, P^k, ...
+  void* seg = nullptr;         // k - 1 grids: recomputed states of one segment
+  int64_t seg_id = -1;
+  bool tape_ok = false;
+  void* init_fields = nullptr; // compute type: rho, ux, uy, uz
+  void* lam[2] = {nullptr, nullptr};
+  int lam_cur = 0;
+  int64_t adj_t = -1;
+  int64_t adj_T = -1;
+};
+
+namespace {
+
+void free_ctx(lbm_ctx* c) {
+  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->partials, c->acc, c->tape,
+                  c->seg,     c->init_fields, c->lam[0], c->lam[1]};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete c;
+}
+
+int32_t validate(const lbm_config* cfg) {
+  if (!cfg) return fail(LBM_EINVAL, "cfg is NULL");
+  if (cfg->stencil < 0 || cfg->stencil > 2) return fail(LBM_EINVAL, "unknown stencil %d", cfg->stencil);
+  if (cfg->method < 0 || cfg->method > 3) return fail(LBM_EINVAL, "unknown method %d", cfg->method);
+  if (cfg->dtype < 0 || cfg->dtype > 3) return fail(LBM_EINVAL, "unknown dtype %d", cfg->dtype);
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+    return fail(LBM_EINVAL, "lattice dims must be >= 1 (got %d x %d x %d)", cfg->nx, cfg->ny, cfg->nz);
+  const int64_t N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+  if (N >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "lattice has %lld cells; the limit is 2^31 - 1", (long long)N);
+  if (cfg->stencil == LBM_D2Q9 && cfg->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (!(std::isfinite(cfg->rho0) && cfg->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be positive");
+  if (cfg->compressible != 0 && cfg->compressible != 1) return fail(LBM_EINVAL, "compressible must be 0 or 1");
+  const lbm_rates& r = cfg->rates;
+  if (!rate_ok(r.omega)) return fail(LBM_EINVAL, "omega = %g is outside (0, 2)", r.omega);
+  if (cfg->method == LBM_TRT) {
+    if (r.omega_odd <= 0) {
+      if (!(std::isfinite(r.magic) && r.magic > 0)) return fail(LBM_EINVAL, "TRT needs omega_odd > 0 or magic > 0");
+      const double wo = 1.0 / (r.magic / (1.0 / r.omega - 0.5) + 0.5);
+      if (!rate_ok(wo)) return fail(LBM_EINVAL, "TRT odd rate from magic = %g is outside (0, 2)", wo);
+    } else if (!rate_ok(r.omega_odd)) {
+      return fail(LBM_EINVAL, "omega_odd = %g is outside (0, 2)", r.omega_odd);
+    }
+  }
+  if (cfg->method == LBM_MRT || cfg->method == LBM_CUMULANT) {
+    if (!rate_ok(r.omega_bulk)) return fail(LBM_EINVAL, "omega_bulk = %g is outside (0, 2)", r.omega_bulk);
+    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
+    for (int i = 0; i < nhi; ++i)
+      if (!rate_ok(r.omega_hi[i])) return fail(LBM_EINVAL, "omega_hi[%d] = %g is outside (0, 2)", i, r.omega_hi[i]);
+  }
+  if (cfg->pattern != 0) return fail(LBM_EUNSUPPORTED, "only the two-array pull pattern (0) is implemented");
+  if (!sweep_supported(cfg->stencil, cfg->method))
+    return fail(LBM_EUNSUPPORTED, "method %d is not implemented on stencil %d", cfg->method, cfg->stencil);
+  if (cfg->method == LBM_CUMULANT) {
+    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
+    for (int i = 0; i < nhi; ++i)
+      if (r.omega_hi[i] != 1.0)
+        return fail(LBM_EUNSUPPORTED, "the cumulant sweep implements higher-order rates equal to 1 only");
+    if (!cfg->compressible) return fail(LBM_EUNSUPPORTED, "the cumulant operator is compressible only");
+  }
+  if (cfg->checkpoint_every < 0) return fail(LBM_EINVAL, "checkpoint_every must be >= 0");
+  if (cfg->checkpoint_every > 0) {
+    if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
+    if (!adjoint_supported(cfg->stencil, cfg->method) || !cfg->compressible)
+      return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT method only");
+  }
+  return LBM_OK;
+}
+
+Geo make_geo(const lbm_config& c) {
+  Geo g;
+  g.nx = c.nx;
+  g.ny = c.ny;
+  g.nz = c.nz;
+  g.nxb = (c.nx + 511) / 512;
+  const int per = (c.nx + g.nxb - 1) / g.nxb;
+  g.bx = ((per + 63) / 64) * 64;
+  g.N = (int64_t)c.nx * c.ny * c.nz;
+  return g;
+}
+
+Params make_params(const lbm_config& c) {
+  Params p;
+  p.rho0 = c.rho0;
+  p.om = c.rates.omega;
+  p.om_b = c.rates.omega_bulk;
+  p.om_o = c.rates.omega_odd > 0 ? c.rates.omega_odd
+                                  : 1.0 / (c.rates.magic / (1.0 / c.rates.omega - 0.5) + 0.5);
+  for (int i = 0; i < 4; ++i) p.hi[i] = c.rates.omega_hi[i];
+  p.compressible = c.compressible;
+  return p;
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+int32_t alloc(void** p, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "hipMalloc of %zu bytes for %s failed: %s", bytes, what, hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+int32_t sweep_once(lbm_ctx* c, const void* src, void* dst) {
+  HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, src, dst, c->flags, c->force, c->g, c->p,
+                       c->has_mask, c->stream),
+          "sweep launch");
+  return LBM_OK;
+}
+
+// Both grids must hold the same values at solid cells: the sweep never
+// writes them, and lbm_get_pdfs reports them from whichever grid is current.
+int32_t mirror_grid(lbm_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->grid[1], c->grid[0], c->grid_bytes, hipMemcpyDeviceToDevice, c->stream), "grid mirror");
+  return LBM_OK;
+}
+
+void reset_time(lbm_ctx* c) {
+  c->t = 0;
+  c->seg_id = -1;
+  c->tape_ok = c->k > 0;
+  c->adj_t = -1;
+  c->adj_T = -1;
+}
+
+int32_t check_field_dtype(int32_t fdt) {
+  if (fdt != LBM_F64 && fdt != LBM_F32) return fail(LBM_EINVAL, "field_dtype must be LBM_F64 or LBM_F32");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_version(void) { return 10000; }
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* hip_stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t st = validate(cfg);
+  if (st != LBM_OK) return st;
+  lbm_ctx* c = new lbm_ctx();
+  c->cfg = *cfg;
+  c->Q = q_of(cfg->stencil);
+  c->g = make_geo(*cfg);
+  c->p = make_params(*cfg);
+  c->stream = (hipStream_t)hip_stream;
+  const size_t N = (size_t)c->g.N;
+  c->grid_bytes = (size_t)c->Q * N * storage_bytes(cfg->dtype);
+  const size_t rb = compute_bytes(cfg->dtype);
+  const int64_t nblk = num_blocks(c->g);
+  auto bail = [&](int32_t s) {
+    free_ctx(c);
+    return s;
+  };
+  for (int i = 0; i < 2; ++i)
+    if ((st = alloc(&c->grid[i], c->grid_bytes, "PDF grid")) != LBM_OK) return bail(st);
+  if ((st = alloc(&c->force, 3 * (size_t)cfg->ny * rb, "force table")) != LBM_OK) return bail(st);
+  if ((st = alloc((void**)&c->partials, (size_t)nblk * 4 * sizeof(double), "reduction partials")) != LBM_OK)
+    return bail(st);
+  if ((st = alloc((void**)&c->acc, 8 * sizeof(double), "accumulators")) != LBM_OK) return bail(st);
+  if (cfg->checkpoint_every > 0) {
+    c->k = cfg->checkpoint_every;
+    c->nslots = (cfg->max_tape_steps - 1) / c->k + 1;
+    if ((st = alloc(&c->tape, c->grid_bytes * (size_t)c->nslots, "checkpoint tape")) != LBM_OK) return bail(st);
+    if (c->k > 1 && (st = alloc(&c->seg, c->grid_bytes * (size_t)(c->k - 1), "segment buffer")) != LBM_OK)
+      return bail(st);
+    if ((st = alloc(&c->init_fields, 4 * N * rb, "initial fields")) != LBM_OK) return bail(st);
+    for (int i = 0; i < 2; ++i)
+      if ((st = alloc(&c->lam[i], (size_t)c->Q * N * rb, "adjoint state")) != LBM_OK) return bail(st);
+  }
+  hipError_t e;
+  if ((e = launch_fill_zero(c->force, 3 * (size_t)cfg->ny * rb, c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "force table init"));
+  if ((e = launch_fill_zero(c->acc, 8 * sizeof(double), c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "accumulator init"));
+  if (solid_mask_host) {
+    c->has_mask = 1;
+    if ((st = alloc((void**)&c->flags, N, "flag field")) != LBM_OK) return bail(st);
+    uint8_t* solid_dev = nullptr;
+    if ((st = alloc((void**)&solid_dev, N, "solid mask staging")) != LBM_OK) return bail(st);
+    e = hipMemcpy(solid_dev, solid_mask_host, N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_build_flags(cfg->stencil, solid_dev, c->flags, c->g, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(solid_dev);
+    if (e != hipSuccess) return bail(hip_fail(e, "solid mask upload"));
+  }
+  if ((e = launch_init(cfg->stencil, cfg->dtype, c->grid[0], c->flags, c->has_mask, nullptr, nullptr, LBM_F64, c->g,
+                       c->p, c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "initial state"));
+  if ((st = mirror_grid(c)) != LBM_OK) return bail(st);
+  reset_time(c);
+  if (c->k > 0) {
+    e = launch_store_init_fields(cfg->dtype, nullptr, nullptr, LBM_F64, c->init_fields, c->g, c->p, c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "initial fields"));
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int32_t lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return LBM_OK;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+  if (e != hipSuccess) return hip_fail(e, "destroy");
+  return LBM_OK;
+}
+
+int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  const int ny = ctx->cfg.ny;
+  std::vector<double> tab(3 * (size_t)ny, 0.0);
+  if (F) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(F[a])) return fail(LBM_EINVAL, "force component %d is not finite", a);
+    for (int y = 0; y < ny; ++y)
+      for (int a = 0; a < 3; ++a) tab[3 * (size_t)y + a] = F[a];
+  } else if (profile_y) {
+    for (size_t i = 0; i < tab.size(); ++i) {
+      if (!std::isfinite(profile_y[i])) return fail(LBM_EINVAL, "force profile entry %zu is not finite", i);
+      tab[i] = profile_y[i];
+    }
+  }
+  if (ctx->cfg.stencil == LBM_D2Q9)
+    for (int y = 0; y < ny; ++y)
+      if (tab[3 * (size_t)y + 2] != 0.0) return fail(LBM_EINVAL, "D2Q9 force must have Fz = 0");
+  if (ctx->cfg.method == LBM_CUMULANT)
+    for (double v : tab)
+      if (v != 0.0) return fail(LBM_EUNSUPPORTED, "body forces are not implemented for the cumulant sweep");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_force sync");
+  if (ctx->cfg.dtype == LBM_F64) {
+    e = hipMemcpy(ctx->force, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> tf(tab.begin(), tab.end());
+    e = hipMemcpy(ctx->force, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "force upload");
+  ctx->tape_ok = false;  // a recorded trajectory no longer matches the force
+  ctx->adj_t = -1;
+  return LBM_OK;
+}
+
+int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev, int32_t field_dtype) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  int32_t st = check_field_dtype(field_dtype);
+  if (st != LBM_OK) return st;
+  ctx->cur = 0;
+  HIP_TRY(launch_init(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, rho_dev, u_dev,
+                      field_dtype, ctx->g, ctx->p, ctx->stream),
+          "init launch");
+  int32_t ms = mirror_grid(ctx);
+  if (ms != LBM_OK) return ms;
+  if (ctx->k > 0)
+    HIP_TRY(launch_store_init_fields(ctx->cfg.dtype, rho_dev, u_dev, field_dtype, ctx->init_fields, ctx->g, ctx->p,
+                                     ctx->stream),
+            "init fields");
+  reset_time(ctx);
+  return LBM_OK;
+}
+
+int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (int32_t i = 0; i < n; ++i) {
+    if (ctx->k > 0 && ctx->t < ctx->cfg.max_tape_steps && ctx->t % ctx->k == 0) {
+      char* slot = (char*)ctx->tape + (size_t)(ctx->t / ctx->k) * ctx->grid_bytes;
+      HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
+              "tape copy");
+    }
+    int32_t st = sweep_once(ctx, ctx->grid[ctx->cur], ctx->grid[ctx->cur ^ 1]);
+    if (st != LBM_OK) return st;
+    ctx->cur ^= 1;
+    ctx->t += 1;
+  }
+  ctx->adj_t = -1;
+  return LBM_OK;
+}
+
+int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t) {
+  if (!ctx || !t) return fail(LBM_EINVAL, "NULL argument");
+  *t = ctx->t;
+  return LBM_OK;
+}
+
+int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t field_dtype) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  int32_t st = check_field_dtype(field_dtype);
+  if (st != LBM_OK) return st;
+  if (!rho_dev && !u_dev) return LBM_OK;
+  HIP_TRY(launch_readout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask, ctx->force,
+                         rho_dev, u_dev, field_dtype, ctx->g, ctx->p, ctx->stream),
+          "readout launch");
+  return LBM_OK;
+}
+
+int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
+  if (!ctx || !out) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(launch_conserved(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+                           ctx->partials, ctx->acc + 4, ctx->g, ctx->p, ctx->stream),
+          "conservation launch");
+  HIP_TRY(hipMemcpyAsync(out, ctx->acc + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "totals copy");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "totals sync");
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(out[i])) return fail(LBM_ENONFINITE, "conservation total %d is not finite", i);
+  return LBM_OK;
+}
+
+int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev) {
+  if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(launch_get_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], pdfs_dev, ctx->g, ctx->p,
+                          ctx->stream),
+          "get_pdfs launch");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "get_pdfs sync");
+  return LBM_OK;
+}
+
+int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev) {
+  if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
+  if (ctx->k > 0) return fail(LBM_ESTATE, "set_pdfs is not available with the adjoint tape (no initial fields)");
+  ctx->cur = 0;
+  HIP_TRY(launch_set_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], pdfs_dev, ctx->g, ctx->p, ctx->stream),
+          "set_pdfs launch");
+  int32_t ms = mirror_grid(ctx);
+  if (ms != LBM_OK) return ms;
+  reset_time(ctx);
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_du_dev, int32_t field_dtype) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  int32_t st = check_field_dtype(field_dtype);
+  if (st != LBM_OK) return st;
+  if (!dL_du_dev) return fail(LBM_EINVAL, "dL_du_dev is NULL");
+  if (ctx->k <= 0) return fail(LBM_ESTATE, "the context was created without a tape (checkpoint_every = 0)");
+  if (!ctx->tape_ok) return fail(LBM_ESTATE, "the tape is invalid (force changed after initialisation)");
+  if (ctx->t > ctx->cfg.max_tape_steps)
+    return fail(LBM_ESTATE, "%lld steps exceed max_tape_steps = %d", (long long)ctx->t, ctx->cfg.max_tape_steps);
+  const size_t lam_bytes = (size_t)ctx->Q * (size_t)ctx->g.N * compute_bytes(ctx->cfg.dtype);
+  HIP_TRY(launch_fill_zero(ctx->lam[1], lam_bytes, ctx->stream), "adjoint state clear");
+  HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+                              ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0], ctx->partials, ctx->g,
+                              ctx->p, ctx->stream),
+          "adjoint seed launch");
+  HIP_TRY(launch_sum_partials(ctx->partials, num_blocks(ctx->g), 3, ctx->acc, 0, ctx->stream), "seed reduction");
+  ctx->lam_cur = 0;
+  ctx->adj_T = ctx->t;
+  ctx->adj_t = ctx->t;
+  ctx->seg_id = -1;
+  return LBM_OK;
+}
+
+namespace {
+
+// Forward state P^s for the adjoint: a tape slot, or a recomputed state of
+// the k-step segment that contains s.
+int32_t forward_state(lbm_ctx* c, int64_t s, const void** out) {
+  const int64_t j = s / c->k, r = s % c->k;
+  const char* slot = (const char*)c->tape + (size_t)j * c->grid_bytes;
+  if (r == 0) {
+    *out = slot;
+    return LBM_OK;
+  }
+  if (c->seg_id != j) {
+    const int64_t last = std::min<int64_t>(c->k - 1, c->adj_T - 1 - j * c->k);
+    const void* src = slot;
+    for (int64_t i = 1; i <= last; ++i) {
+      void* dst = (char*)c->seg + (size_t)(i - 1) * c->grid_bytes;
+      int32_t st = sweep_once(c, src, dst);
+      if (st != LBM_OK) return st;
+      src = dst;
+    }
+    c->seg_id = j;
+  }
+  *out = (const char*)c->seg + (size_t)(r - 1) * c->grid_bytes;
+  return LBM_OK;
+}
+
+}  // namespace
+
+int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (ctx->adj_t < 0) return fail(LBM_ESTATE, "no adjoint seeded (or the forward state changed since)");
+  if (n > ctx->adj_t) return fail(LBM_ESTATE, "%d adjoint steps requested, %lld remain", n, (long long)ctx->adj_t);
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t s = ctx->adj_t - 1;
+    const void* P = nullptr;
+    int32_t st = forward_state(ctx, s, &P);
+    if (st != LBM_OK) return st;
+    HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, P, ctx->flags, ctx->has_mask, ctx->force,
+                                 ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->partials, ctx->g, ctx->p,
+                                 ctx->stream),
+            "adjoint sweep launch");
+    HIP_TRY(launch_sum_partials(ctx->partials, num_blocks(ctx->g), 3, ctx->acc, 1, ctx->stream),
+            "adjoint reduction");
+    ctx->lam_cur ^= 1;
+    ctx->adj_t -= 1;
+  }
+  return LBM_OK;
+}
+
+int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev, int32_t field_dtype, double* dL_dF) {
+  if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+  int32_t st = check_field_dtype(field_dtype);
+  if (st != LBM_OK) return st;
+  if (ctx->adj_t != 0) return fail(LBM_ESTATE, "the adjoint has not reached t = 0");
+  if (dL_du0_dev || dL_drho0_dev)
+    HIP_TRY(launch_adjoint_init_grad(ctx->cfg.stencil, ctx->cfg.dtype, ctx->lam[ctx->lam_cur], ctx->flags,
+                                     ctx->has_mask, ctx->init_fields, dL_du0_dev, dL_drho0_dev, field_dtype, ctx->g,
+                                     ctx->p, ctx->stream),
+            "init gradient launch");
+  if (dL_dF) {
+    HIP_TRY(hipMemcpyAsync(dL_dF, ctx->acc, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "dL/dF copy");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "dL/dF sync");
+  }
+  return LBM_OK;
+}
+
+int32_t lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q, int32_t elem_bytes, void* hip_stream) {
+  if (!src_dev || !dst_dev) return fail(LBM_EINVAL, "NULL buffer");
+  if (n < 1 || q < 1) return fail(LBM_EINVAL, "n and q must be >= 1");
+  if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return fail(LBM_EINVAL, "elem_bytes must be 2, 4 or 8");
+  HIP_TRY(launch_copy_q(src_dev, dst_dev, n, q, elem_bytes, (hipStream_t)hip_stream), "copy_q launch");
+  return LBM_OK;
+}
+
+}  // extern "C"

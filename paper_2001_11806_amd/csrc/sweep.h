@@ -1,0 +1,156 @@
+// The fused stream-pull-collide sweep (two-array pattern).
+//
+// Paper, Sec. IV-B and Fig. "stream-pull-collide": every cell pulls
+// population q from its upstream neighbour x - c_q in the source array,
+// collides locally and writes all Q results to its own slot in the
+// destination array.  Halfway bounce-back for resting walls (Sec. III-C
+// "Boundary Conditions", wall velocity 0) is compiled into the gather
+// (Sec. IV-B "Boundary Conditions", flag field variant): if x - c_q is solid
+// the cell reads its own outgoing population opp(q) instead.
+//
+// MI355X mapping
+//   - structure-of-arrays layout P[q][z][y][x]; a wavefront reads 64
+//     consecutive x of one q-plane per load, so every load and store is
+//     coalesced; the +-1 x offset of the pull is absorbed by the cache line
+//     that the neighbouring lanes fetch anyway;
+//   - one block per x-row (or per x-segment of at most 512 cells), so each
+//     source row of each q-plane is read by exactly one block: the pull
+//     touches every stored byte exactly once, 2 Q s bytes per cell update;
+//   - all Q loads are issued before any arithmetic (full unroll), which keeps
+//     Q * 64 loads in flight per wave;
+//   - the per-cell flag byte (bit 0 solid, bit 1 "fluid cell next to a
+//     solid") keeps the neighbour-mask reads off the path of interior cells;
+//   - periodic wrap by compare-and-select on the three neighbour coordinates.
+#pragma once
+
+#include "collide.h"
+#include "internal.h"
+#include "lattice.h"
+#include "storage.h"
+
+namespace lbm {
+
+template <class R>
+inline CollideParams<R> to_collide_params(const Params& p) {
+  CollideParams<R> c;
+  c.rho0 = R(p.rho0);
+  c.om = R(p.om);
+  c.om_b = R(p.om_b);
+  c.om_o = R(p.om_o);
+  for (int i = 0; i < 4; ++i) c.hi[i] = R(p.hi[i]);
+  c.compressible = p.compressible;
+  return c;
+}
+
+// Thread -> cell mapping shared by all per-cell kernels.
+struct CellIdx {
+  int x, y, z, cell;
+  bool valid;
+};
+
+__device__ __forceinline__ CellIdx cell_of(const Geo& g) {
+  CellIdx c;
+  const int seg = blockIdx.x % g.nxb;
+  const int row = blockIdx.x / g.nxb;
+  c.x = seg * g.bx + threadIdx.x;
+  c.y = row % g.ny;
+  c.z = row / g.ny;
+  c.cell = row * g.nx + c.x;
+  c.valid = c.x < g.nx;
+  return c;
+}
+
+// Linear index of the upstream cell x - c for direction q (periodic).
+template <class L>
+__device__ __forceinline__ int upstream(int q, const CellIdx& c, const Geo& g, int xm, int xp, int ym,
+                                        int yp, int zm, int zp) {
+  const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+  const int sx = cx > 0 ? xm : (cx < 0 ? xp : c.x);
+  const int sy = cy > 0 ? ym : (cy < 0 ? yp : c.y);
+  const int sz = cz > 0 ? zm : (cz < 0 ? zp : c.z);
+  return (sz * g.ny + sy) * g.nx + sx;
+}
+
+#define LBM_NEIGHBOURS(c, g)                                        \
+  const int xm = ((c).x == 0 ? (g).nx : (c).x) - 1;                 \
+  const int xp = ((c).x + 1 == (g).nx) ? 0 : (c).x + 1;             \
+  const int ym = ((c).y == 0 ? (g).ny : (c).y) - 1;                 \
+  const int yp = ((c).y + 1 == (g).ny) ? 0 : (c).y + 1;             \
+  const int zm = ((c).z == 0 ? (g).nz : (c).z) - 1;                 \
+  const int zp = ((c).z + 1 == (g).nz) ? 0 : (c).z + 1;
+
+// Pull-gather of the Q pre-collision populations of one fluid cell, with
+// halfway bounce-back.  Bit q of *bb is set when link q was bounced.
+template <class L, class T>
+__device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t* __restrict__ flags, int fl,
+                                       const CellIdx& c, const Geo& g, typename Storage<T>::R* f,
+                                       uint32_t* bb, int* up) {
+  LBM_NEIGHBOURS(c, g)
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int sc = upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp);
+    if (up) up[q] = sc;
+    const T* ptr = src + (size_t)q * (size_t)g.N + sc;
+    if (fl & 2) {
+      if (flags[sc] & 1) {
+        ptr = src + (size_t)opp<L>(q) * (size_t)g.N + c.cell;
+        m |= 1u << q;
+      }
+    }
+    f[q] = Storage<T>::load(ptr);
+  }
+  if (bb) *bb = m;
+}
+
+template <class L, int M, class T>
+__global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __restrict__ dst,
+                                               const uint8_t* __restrict__ flags,
+                                               const typename Storage<T>::R* __restrict__ force_y, Geo g,
+                                               CollideParams<typename Storage<T>::R> p, int has_mask) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  int fl = 0;
+  if (has_mask) {
+    fl = flags[c.cell];
+    if (fl & 1) return;  // solid cells are never updated
+  }
+  R f[L::Q];
+  gather<L, T>(src, flags, fl, c, g, f, nullptr, nullptr);
+  const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
+  collide<L, M>(f, F, p);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) Storage<T>::store(dst + (size_t)q * (size_t)g.N + c.cell, f[q]);
+}
+
+template <class L, int M, class T>
+hipError_t run_sweep(const void* src, void* dst, const uint8_t* flags, const void* force_y, const Geo& g,
+                     const Params& p, int has_mask, hipStream_t s) {
+  using R = typename Storage<T>::R;
+  const CollideParams<R> cp = to_collide_params<R>(p);
+  hipLaunchKernelGGL((k_sweep<L, M, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
+                     (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
+  return hipGetLastError();
+}
+
+template <class L, int M>
+hipError_t sweep_for_dtype(int dtype, const void* src, void* dst, const uint8_t* flags, const void* force_y,
+                           const Geo& g, const Params& p, int has_mask, hipStream_t s) {
+  switch (dtype) {
+    case 0: return run_sweep<L, M, double>(src, dst, flags, force_y, g, p, has_mask, s);
+    case 1: return run_sweep<L, M, float>(src, dst, flags, force_y, g, p, has_mask, s);
+    case 2: return run_sweep<L, M, __bf16>(src, dst, flags, force_y, g, p, has_mask, s);
+    case 3: return run_sweep<L, M, _Float16>(src, dst, flags, force_y, g, p, has_mask, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_d2q9(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+                             const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
+hipError_t launch_sweep_d3q19(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+                              const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
+hipError_t launch_sweep_d3q27(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+                              const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
+
+}  // namespace lbm

@@ -105,17 +105,18 @@ def solenoidal_modes(seed=3, nmodes=32, kmax=4, umax=0.05):
 
 
 def solenoidal_velocity(n, modes, dtype=np.float64):
-    """Evaluate ``solenoidal_modes`` on the full n^3 periodic lattice."""
+    """Evaluate ``solenoidal_modes`` on the full n^3 periodic lattice.
+
+    Each mode factorises as exp(i k_z z') exp(i (k_y y' + k_x x')), so the
+    sum over modes is one complex matrix product per component."""
     ks, amps, phis = modes
-    u = np.zeros((3, n, n, n), dtype=dtype)
     r = np.arange(n, dtype=np.float64) * (2 * np.pi / n)
-    for k, a, ph in zip(ks, amps, phis):
-        ex = np.exp(1j * k[0] * r)[None, None, :]
-        ey = np.exp(1j * k[1] * r)[None, :, None]
-        ez = np.exp(1j * (k[2] * r + 0.0))[:, None, None] * np.exp(1j * ph)
-        phase = (ez * ey * ex).real.astype(dtype)
-        for c in range(3):
-            u[c] += (a[c] * phase).astype(dtype)
+    Ez = np.exp(1j * (np.outer(ks[:, 2], r) + phis[:, None]))                  # (M, nz)
+    Exy = (np.exp(1j * np.outer(ks[:, 1], r))[:, :, None]
+           * np.exp(1j * np.outer(ks[:, 0], r))[:, None, :]).reshape(len(ks), -1)   # (M, ny*nx)
+    u = np.empty((3, n, n, n), dtype=dtype)
+    for c in range(3):
+        u[c] = (((amps[:, c:c + 1] * Ez).T @ Exy).real).reshape(n, n, n)
     return u
 
 

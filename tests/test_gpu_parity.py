@@ -1,0 +1,165 @@
+"""GPU parity of the HIP sweep against the FP64 oracle on small ragged
+lattices (several tiles plus a ragged tail in x, walls, solid cells and a
+body force), for every implemented stencil x method x storage type.
+
+Bars: FP64 storage agrees with the oracle to roundoff (|dP| <= 1e-13,
+relative L2 of u <= 1e-12); shifted FP32 storage within 1e-5 relative L2 of
+u; after a single step every stored value is within one storage ulp (plus
+the FP32 compute error) of the oracle that rounds the same way; BF16/FP16
+multi-step errors are reported against stated bounds.
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import (RATES, case_dims, make_gpu, need_gpu, oracle_cfg, rel_l2, seeded_fields,
+                              to_np, torch, ulp_of)
+from oracle import run as orun
+
+pytestmark = pytest.mark.gpu
+
+COMBOS = [("D2Q9", "SRT"), ("D2Q9", "TRT"), ("D2Q9", "MRT"), ("D2Q9", "CUMULANT"),
+          ("D3Q19", "SRT"), ("D3Q19", "TRT"),
+          ("D3Q27", "SRT"), ("D3Q27", "TRT"), ("D3Q27", "MRT"), ("D3Q27", "CUMULANT")]
+DTYPES = ["f64", "f32", "bf16", "f16"]
+MRT_RATES = dict(RATES, omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.1, 0.9, 1.3, 1.05))
+CUM_RATES = dict(RATES, omega=1 / 0.55, omega_bulk=1.1, omega_hi=(1.0, 1.0, 1.0, 1.0))
+
+# stated multi-step bounds (relative L2 of u after STEPS steps, vs plain FP64)
+STEPS = 12
+BOUND_U = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-2, "f16": 3e-3}
+
+
+def _rates(method):
+    return MRT_RATES if method == "MRT" else (CUM_RATES if method == "CUMULANT" else RATES)
+
+
+def _setup(stencil, method, dtype, seed=1):
+    dims = case_dims(stencil)
+    cum = method == "CUMULANT"
+    mask, rho, u = seeded_fields(stencil, dims, seed, with_mask=not cum)
+    F = None if cum else np.array([2e-4, -1e-4, 0.0 if stencil == "D2Q9" else 5e-5])
+    return dims, mask, rho, u, F
+
+
+def _run_pair(stencil, method, dtype, steps, emulate):
+    dims, mask, rho, u, F = _setup(stencil, method, dtype)
+    rates = _rates(method)
+    print("case", stencil, method, dtype, dims, "steps", steps, flush=True)
+    g = make_gpu(stencil, method, dtype, dims, mask, rates)
+    if F is not None:
+        g.set_force(F)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(steps)
+    P_gpu = to_np(g.get_pdfs())
+    rho_g, u_g = (to_np(t) for t in g.macroscopic())
+    g.close()
+    cfg = oracle_cfg(stencil, method, dtype if emulate else "f64", rates)
+    Ff = orun.force_field(F, dims)
+    P = orun.init_equilibrium(cfg, rho, u, mask)
+    P = orun.run(cfg, P, steps, mask, Ff)
+    rho_o, u_o = orun.readout(cfg, P, mask, Ff)
+    return P_gpu, P, (rho_g, u_g), (rho_o, u_o), mask
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("stencil,method", COMBOS)
+def test_multi_step_parity(stencil, method, dtype):
+    need_gpu()
+    P_gpu, P_ora, (rg, ug), (ro, uo), mask = _run_pair(stencil, method, dtype, STEPS, emulate=False)
+    err_u = rel_l2(ug, uo)
+    fluid = ro != 0
+    err_r = rel_l2(rg[fluid] - 1.0, ro[fluid] - 1.0)
+    print("rel L2 u %.3e  rho-1 %.3e" % (err_u, err_r))
+    assert err_u <= BOUND_U[dtype], err_u
+    if dtype == "f64":
+        assert np.max(np.abs(P_gpu - P_ora)) <= 1e-13
+        assert err_r <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("stencil,method", COMBOS)
+def test_one_step_within_storage_ulp(stencil, method, dtype):
+    """One step from the same rounded initial state: each stored value is
+    within one storage ulp of the oracle that rounds identically, plus the
+    FP32 compute error (bounded by 4e-7, about 7 units of 2^-24, of the
+    largest shifted value in the lattice)."""
+    need_gpu()
+    P_gpu, P_ora, _, _, mask = _run_pair(stencil, method, dtype, 1, emulate=True)
+    w = oracle_cfg(stencil, method, dtype).lat.w.reshape(-1, 1, 1, 1)
+    sg, so = P_gpu - w, P_ora - w
+    tol = ulp_of(so, dtype) + 4e-7 * np.max(np.abs(so))
+    bad = np.abs(sg - so) > tol
+    assert not bad.any(), (np.argwhere(bad)[:5], np.abs(sg - so)[bad][:5], tol[bad][:5])
+
+
+@pytest.mark.parametrize("stencil,method", COMBOS)
+def test_init_readout_and_totals(stencil, method):
+    need_gpu()
+    dims, mask, rho, u, F = _setup(stencil, method, "f64")
+    rates = _rates(method)
+    g = make_gpu(stencil, method, "f64", dims, mask, rates)
+    if F is not None:
+        g.set_force(F)
+    rho32, u32 = rho.astype(np.float32), u.astype(np.float32)     # exercises the FP32 field path
+    g.init_equilibrium(torch.tensor(rho32), torch.tensor(u32))
+    cfg = oracle_cfg(stencil, method, "f64", rates)
+    P = orun.init_equilibrium(cfg, rho32.astype(np.float64), u32.astype(np.float64), mask)
+    np.testing.assert_allclose(to_np(g.get_pdfs()), P, rtol=0, atol=2e-16)
+    Ff = orun.force_field(F, dims)
+    rg, ug = (to_np(t) for t in g.macroscopic())
+    ro, uo = orun.readout(cfg, P, mask, Ff)
+    np.testing.assert_allclose(rg, ro, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ug, uo, rtol=0, atol=1e-16)
+    tot = g.conserved()
+    np.testing.assert_allclose(tot, orun.conserved(cfg, P, mask), rtol=1e-14, atol=1e-13)
+    g.step(5)
+    tot5 = g.conserved()
+    assert abs(tot5[0] / tot[0] - 1) < 1e-14   # mass: streaming is a permutation
+    g.close()
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_solid_cells_untouched_any_step_count(steps):
+    """Solid cells keep their initial (rest) state on whichever grid is
+    current, after odd and even step counts."""
+    need_gpu()
+    dims, mask, rho, u, F = _setup("D3Q19", "TRT", "f32")
+    g = make_gpu("D3Q19", "TRT", "f32", dims, mask, RATES)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(steps)
+    P = to_np(g.get_pdfs())
+    g.close()
+    w = oracle_cfg("D3Q19", "TRT", "f32").lat.w
+    s = mask.astype(bool)
+    for q in range(19):
+        assert np.all(P[q][s] == w[q])
+
+
+def test_zero_steps_and_set_pdfs_roundtrip():
+    need_gpu()
+    dims = (70, 6, 4)
+    g = make_gpu("D3Q19", "TRT", "f64", dims, None)
+    rng = np.random.default_rng(3)
+    P = orun.init_equilibrium(oracle_cfg("D3Q19", "TRT", "f64"), np.ones((4, 6, 70)),
+                              0.02 * rng.standard_normal((3, 4, 6, 70)))
+    g.set_pdfs(torch.tensor(P))
+    g.step(0)
+    assert g.time == 0
+    np.testing.assert_allclose(to_np(g.get_pdfs()), P, rtol=0, atol=1e-16)
+    g.close()
+
+
+def test_x_extent_one_and_wide_rows():
+    """nx = 1 (every x-neighbour is the cell itself) and nx > 512 (several
+    blocks per row) both match the oracle."""
+    need_gpu()
+    for dims in ((1, 12, 3), (1100, 3, 2)):
+        mask, rho, u = seeded_fields("D3Q19", dims, 5)
+        g = make_gpu("D3Q19", "SRT", "f64", dims, mask)
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+        g.step(4)
+        cfg = oracle_cfg("D3Q19", "SRT", "f64")
+        P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), 4, mask)
+        assert np.max(np.abs(to_np(g.get_pdfs()) - P)) <= 1e-14
+        g.close()
