@@ -118,9 +118,8 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
   if (c.valid && has_mask) fl = flags[c.cell];
   if (c.valid && !(fl & 1)) {
     R f[L::Q];
-    int up[L::Q];
     uint32_t bb = 0;
-    gather<L, T>(P, flags, fl, c, g, f, &bb, up);
+    gather<L, T>(P, flags, fl, c, g, f, &bb);
     R lam[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];
@@ -157,11 +156,23 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
     bz -= R(3) * (om * rho * uz + fs * F2) * s0;
     const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
     const R one_m = R(1) - om;
+    // h goes back along the link it was pulled through: the upstream slot
+    // (x - c_q, q), addressed like the gather; a bounced link's upstream slot
+    // belongs to a solid cell (written at most once, never read) and its
+    // value goes to (x, opp(q)) instead.
+    LBM_NEIGHBOURS(c, g)
+    const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(R), (uint32_t)c.x * (uint32_t)sizeof(R),
+                            (uint32_t)xm * (uint32_t)sizeof(R)};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      const R h = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
-      const size_t dst = (bb >> q) & 1u ? (size_t)opp<L>(q) * N + c.cell : (size_t)q * N + up[q];
-      lam_out[dst] = h;
+      lam[q] = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
+      R* row = const_cast<R*>(row_base<L>((const R*)lam_out, q, c.y, c.z, ym, yp, zm, zp, g));
+      *at_bytes(row, ox[L::c(q, 0) + 1]) = lam[q];
+    }
+    if (bb) {
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q)
+        if ((bb >> q) & 1u) lam_out[(size_t)opp<L>(q) * N + c.cell] = lam[q];
     }
     dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
     dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);

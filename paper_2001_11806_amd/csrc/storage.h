@@ -20,6 +20,7 @@ struct Storage<double> {
   static constexpr int code = 0;
   __device__ static R load(const double* p) { return *p; }
   __device__ static void store(double* p, R v) { *p = v; }
+  __device__ static void store_nt(double* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
@@ -28,6 +29,7 @@ struct Storage<float> {
   static constexpr int code = 1;
   __device__ static R load(const float* p) { return *p; }
   __device__ static void store(float* p, R v) { *p = v; }
+  __device__ static void store_nt(float* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
@@ -36,6 +38,7 @@ struct Storage<__bf16> {
   static constexpr int code = 2;
   __device__ static R load(const __bf16* p) { return static_cast<float>(*p); }
   __device__ static void store(__bf16* p, R v) { *p = static_cast<__bf16>(v); }
+  __device__ static void store_nt(__bf16* p, R v) { __builtin_nontemporal_store(static_cast<__bf16>(v), p); }
 };
 
 template <>
@@ -44,6 +47,7 @@ struct Storage<_Float16> {
   static constexpr int code = 3;
   __device__ static R load(const _Float16* p) { return static_cast<float>(*p); }
   __device__ static void store(_Float16* p, R v) { *p = static_cast<_Float16>(v); }
+  __device__ static void store_nt(_Float16* p, R v) { __builtin_nontemporal_store(static_cast<_Float16>(v), p); }
 };
 
 }  // namespace lbm

@@ -79,31 +79,82 @@ __device__ __forceinline__ int upstream(int q, const CellIdx& c, const Geo& g, i
   const int zm = ((c).z == 0 ? (g).nz : (c).z) - 1;                 \
   const int zp = ((c).z + 1 == (g).nz) ? 0 : (c).z + 1;
 
-// Pull-gather of the Q pre-collision populations of one fluid cell, with
-// halfway bounce-back.  Bit q of *bb is set when link q was bounced.
+// Addressing.  A block covers one x-segment of one (y, z) row, so y, z and
+// every neighbour row index are wave-uniform: the start of the source row of
+// plane q, src + q N + row(y - c_y, z - c_z) nx, is computed in scalar
+// registers, and each lane adds one of three 32-bit byte offsets (x - c_x
+// with periodic wrap).  The loads then use the scalar-base + vector-offset
+// form and cost no 64-bit vector address arithmetic.
+template <class T>
+__device__ __forceinline__ const T* at_bytes(const T* base, uint32_t off) {
+  return (const T*)((const char*)base + off);
+}
+template <class T>
+__device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
+  return (T*)((char*)base + off);
+}
+
+template <class L, class T>
+__device__ __forceinline__ const T* row_base(const T* src, int q, int y, int z, int ym, int yp, int zm, int zp,
+                                             const Geo& g) {
+  const int cy = L::c(q, 1), cz = L::c(q, 2);
+  const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
+  const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
+  return src + (size_t)q * (size_t)g.N + (size_t)(sz * g.ny + sy) * (size_t)g.nx;
+}
+
+// Pull-gather of the Q pre-collision populations of one fluid cell with
+// halfway bounce-back.  Every link first loads its upstream slot (for a
+// bounced link that slot belongs to a solid cell: in bounds, value unused);
+// cells next to a wall (flag bit 1) then replace the bounced links by their
+// own outgoing population opp(q).  Bit q of *bb is set for bounced links.
 template <class L, class T>
 __device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t* __restrict__ flags, int fl,
-                                       const CellIdx& c, const Geo& g, typename Storage<T>::R* f,
-                                       uint32_t* bb, int* up) {
+                                       const CellIdx& c, const Geo& g, typename Storage<T>::R* f, uint32_t* bb) {
   LBM_NEIGHBOURS(c, g)
-  uint32_t m = 0;
+  const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(T), (uint32_t)c.x * (uint32_t)sizeof(T),
+                          (uint32_t)xm * (uint32_t)sizeof(T)};  // source x for c_x = -1, 0, +1
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const int sc = upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp);
-    if (up) up[q] = sc;
-    const T* ptr = src + (size_t)q * (size_t)g.N + sc;
-    if (fl & 2) {
-      if (flags[sc] & 1) {
-        ptr = src + (size_t)opp<L>(q) * (size_t)g.N + c.cell;
+  for (int q = 0; q < L::Q; ++q)
+    f[q] = Storage<T>::load(at_bytes(row_base<L>(src, q, c.y, c.z, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]));
+  uint32_t m = 0;
+  if (fl & 2) {
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+      const int sx = cx > 0 ? xm : (cx < 0 ? xp : c.x);
+      const int sy = cy > 0 ? ym : (cy < 0 ? yp : c.y);
+      const int sz = cz > 0 ? zm : (cz < 0 ? zp : c.z);
+      if (flags[(sz * g.ny + sy) * g.nx + sx] & 1) {
+        f[q] = Storage<T>::load(src + (size_t)opp<L>(q) * (size_t)g.N + c.cell);
         m |= 1u << q;
       }
     }
-    f[q] = Storage<T>::load(ptr);
   }
   if (bb) *bb = m;
 }
 
-template <class L, int M, class T>
+// Store the Q post-collision values of a cell into its own slots; NT = 1
+// marks them non-temporal (the lattice is far larger than the caches and
+// the next reader is the next launch).
+template <class T, int NT>
+__device__ __forceinline__ void store_cell(T* __restrict__ dst, const CellIdx& c, const Geo& g,
+                                           const typename Storage<T>::R* f, int Q) {
+  T* row = dst + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+  const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    if (q < Q) {
+      T* p = at_bytes(row + (size_t)q * (size_t)g.N, ox);
+      if (NT)
+        Storage<T>::store_nt(p, f[q]);
+      else
+        Storage<T>::store(p, f[q]);
+    }
+  }
+}
+
+template <class L, int M, class T, int NT>
 __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __restrict__ dst,
                                                const uint8_t* __restrict__ flags,
                                                const typename Storage<T>::R* __restrict__ force_y, Geo g,
@@ -117,11 +168,10 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
     if (fl & 1) return;  // solid cells are never updated
   }
   R f[L::Q];
-  gather<L, T>(src, flags, fl, c, g, f, nullptr, nullptr);
+  gather<L, T>(src, flags, fl, c, g, f, nullptr);
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) Storage<T>::store(dst + (size_t)q * (size_t)g.N + c.cell, f[q]);
+  store_cell<T, NT>(dst, c, g, f, L::Q);
 }
 
 template <class L, int M, class T>
@@ -129,8 +179,14 @@ hipError_t run_sweep(const void* src, void* dst, const uint8_t* flags, const voi
                      const Params& p, int has_mask, hipStream_t s) {
   using R = typename Storage<T>::R;
   const CollideParams<R> cp = to_collide_params<R>(p);
-  hipLaunchKernelGGL((k_sweep<L, M, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
-                     (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
+  // non-temporal stores once the two grids clearly exceed the on-chip caches
+  const bool nt = (size_t)g.N * L::Q * sizeof(T) > (size_t(512) << 20);
+  if (nt)
+    hipLaunchKernelGGL((k_sweep<L, M, T, 1>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
+                       (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
+  else
+    hipLaunchKernelGGL((k_sweep<L, M, T, 0>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
+                       (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
   return hipGetLastError();
 }
 
