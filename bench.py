@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,copy,c3,c4,c5)")
+    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,copy,c1,c3,c4,c5)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU halo exchange is not built "
@@ -199,6 +199,9 @@ def main():
         del ref, u3
         torch.cuda.empty_cache()
 
+    if want("c1"):
+        extras["c1_d2q9_srt_64_f64"] = bench_c1(torch, LBM, inputs, Timer)
+
     if want("c4"):
         extras["c4_d3q19_srt_adjoint_128_f32"] = bench_adjoint(torch, LBM, inputs, Timer)
         torch.cuda.empty_cache()
@@ -256,6 +259,25 @@ def main():
         "wall_s": round(time.time() - t_start, 1),
     }
     print(json.dumps(result))
+
+
+def bench_c1(torch, LBM, inputs, Timer):
+    """C1: D2Q9 SRT 64^2 Taylor-Green, FP64, 1000 steps; launch-latency bound,
+    so the graph replay (launch_mode 0) is timed beside direct launches."""
+    rho, u = inputs.taylor_green_2d(64, 0.01)
+    out = {}
+    for mode, name in ((0, "graph"), (1, "direct")):
+        lbm = LBM("D2Q9", "SRT", "f64", (64, 64, 1), 1 / 0.8, launch_mode=mode)
+        lbm.init_equilibrium(torch.from_numpy(rho), torch.from_numpy(u))
+        lbm.step(64)
+        with Timer(torch, lbm.stream) as t:
+            lbm.step(1000)
+        lbm.close()
+        out[name + "_mlups"] = 64 * 64 * 1000 / (t.ms / 1e3) / 1e6
+        out[name + "_us_per_step"] = t.ms
+    log("C1 D2Q9 64^2: graph %.0f MLUPS (%.2f us/step), direct %.0f MLUPS (%.2f us/step)" % (
+        out["graph_mlups"], out["graph_us_per_step"], out["direct_mlups"], out["direct_us_per_step"]))
+    return out
 
 
 def bench_adjoint(torch, LBM, inputs, Timer):

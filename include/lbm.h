@@ -90,6 +90,9 @@ typedef struct {
   int32_t pattern;          /* 0: two-array pull (the only pattern implemented)     */
   int32_t checkpoint_every; /* k > 0 enables the adjoint tape (PDF copy every k steps) */
   int32_t max_tape_steps;   /* longest forward run the tape covers (adjoint only)   */
+  int32_t launch_mode;      /* 0: automatic -- lattices of at most 64 MiB per grid without a
+                               tape replay a captured HIP graph of 32 sweeps (launch latency
+                               dominates there); 1: one direct launch per step      */
 } lbm_config;
 
 /* Supported combinations: SRT, TRT on all stencils; MRT on D2Q9 and D3Q27;
@@ -121,7 +124,8 @@ int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
 int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
                              int32_t field_dtype);
 
-/* Advance n >= 0 time steps (one fused stream-pull-collide launch each).
+/* Advance n >= 0 time steps (one fused stream-pull-collide launch each;
+ * with launch_mode 0 small lattices replay a captured graph of 32 launches).
  * With the tape enabled, the state at every multiple of k steps below
  * max_tape_steps is copied into the tape first. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t n);

@@ -103,6 +103,9 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
 }
 
 // ------------------------------------------------------------------ sweep
+// Each block adds its dL/dF contribution to its own FP64 accumulator slot
+// (only that block's thread 0 touches the slot, launches are stream-ordered),
+// so the sum is deterministic and needs no reduction launch per step.
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                    int has_mask, const typename Storage<T>::R* __restrict__ force_y,
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
   }
   block_sum_adj<3>(dF);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] = dF[k];
+    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] += dF[k];
 }
 
 // ------------------------------------------------------------------ init

@@ -53,6 +53,7 @@ struct lbm_ctx {
   void* force = nullptr;       // compute type, 3 * ny
   double* partials = nullptr;  // 4 doubles per block
   double* acc = nullptr;       // [0..2] adjoint dL/dF, [4..7] conservation totals
+  double* adj_acc = nullptr;   // 3 doubles per block: dL/dF accumulated over adjoint steps
   int64_t t = 0;
   // tape
   int k = 0;
@@ -66,12 +67,21 @@ struct lbm_ctx {
   int lam_cur = 0;
   int64_t adj_t = -1;
   int64_t adj_T = -1;
+  // graph replay for small lattices: one executable graph per starting grid
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
 };
 
 namespace {
 
+constexpr int kGraphSteps = 32;                 // even: the current grid is unchanged after a replay
+constexpr size_t kGraphMaxGridBytes = size_t(64) << 20;
+
 void free_ctx(lbm_ctx* c) {
-  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->partials, c->acc, c->tape,
+  for (auto& ge : c->graph_exec)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->partials, c->acc, c->adj_acc, c->tape,
                   c->seg,     c->init_fields, c->lam[0], c->lam[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -117,6 +127,7 @@ int32_t validate(const lbm_config* cfg) {
         return fail(LBM_EUNSUPPORTED, "the cumulant sweep implements higher-order rates equal to 1 only");
     if (!cfg->compressible) return fail(LBM_EUNSUPPORTED, "the cumulant operator is compressible only");
   }
+  if (cfg->launch_mode != 0 && cfg->launch_mode != 1) return fail(LBM_EINVAL, "launch_mode must be 0 or 1");
   if (cfg->checkpoint_every < 0) return fail(LBM_EINVAL, "checkpoint_every must be >= 0");
   if (cfg->checkpoint_every > 0) {
     if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
@@ -170,6 +181,40 @@ int32_t sweep_once(lbm_ctx* c, const void* src, void* dst) {
   HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, src, dst, c->flags, c->force, c->g, c->p,
                        c->has_mask, c->stream),
           "sweep launch");
+  return LBM_OK;
+}
+
+bool graph_replay(const lbm_ctx* c) {
+  return c->cfg.launch_mode == 0 && c->k == 0 && c->grid_bytes <= kGraphMaxGridBytes;
+}
+
+// Capture kGraphSteps sweeps starting from grid `parity` on a private stream
+// (capture is not possible on the legacy null stream); the executable graph
+// is then launched on the context's stream.  Kernels only: no memset nodes.
+int32_t ensure_graph(lbm_ctx* c, int parity) {
+  if (c->graph_exec[parity]) return LBM_OK;
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  int cur = parity;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) {
+    e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, c->grid[cur], c->grid[cur ^ 1], c->flags,
+                     c->force, c->g, c->p, c->has_mask, c->cap_stream);
+    cur ^= 1;
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(e, "captured sweep launch");
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+  e = hipGraphInstantiate(&c->graph_exec[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->graph_exec[parity] = nullptr;
+    return hip_fail(e, "graph instantiate");
+  }
   return LBM_OK;
 }
 
@@ -233,6 +278,8 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
     if (c->k > 1 && (st = alloc(&c->seg, c->grid_bytes * (size_t)(c->k - 1), "segment buffer")) != LBM_OK)
       return bail(st);
     if ((st = alloc(&c->init_fields, 4 * N * rb, "initial fields")) != LBM_OK) return bail(st);
+    if ((st = alloc((void**)&c->adj_acc, (size_t)nblk * 3 * sizeof(double), "dL/dF accumulators")) != LBM_OK)
+      return bail(st);
     for (int i = 0; i < 2; ++i)
       if ((st = alloc(&c->lam[i], (size_t)c->Q * N * rb, "adjoint state")) != LBM_OK) return bail(st);
   }
@@ -329,7 +376,16 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
 int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
   if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  for (int32_t i = 0; i < n; ++i) {
+  int32_t i = 0;
+  if (graph_replay(ctx)) {
+    for (; n - i >= kGraphSteps; i += kGraphSteps) {
+      int32_t st = ensure_graph(ctx, ctx->cur);
+      if (st != LBM_OK) return st;
+      HIP_TRY(hipGraphLaunch(ctx->graph_exec[ctx->cur], ctx->stream), "graph launch");
+      ctx->t += kGraphSteps;
+    }
+  }
+  for (; i < n; ++i) {
     if (ctx->k > 0 && ctx->t < ctx->cfg.max_tape_steps && ctx->t % ctx->k == 0) {
       char* slot = (char*)ctx->tape + (size_t)(ctx->t / ctx->k) * ctx->grid_bytes;
       HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
@@ -407,10 +463,9 @@ int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_d
   const size_t lam_bytes = (size_t)ctx->Q * (size_t)ctx->g.N * compute_bytes(ctx->cfg.dtype);
   HIP_TRY(launch_fill_zero(ctx->lam[1], lam_bytes, ctx->stream), "adjoint state clear");
   HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
-                              ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0], ctx->partials, ctx->g,
+                              ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0], ctx->adj_acc, ctx->g,
                               ctx->p, ctx->stream),
           "adjoint seed launch");
-  HIP_TRY(launch_sum_partials(ctx->partials, num_blocks(ctx->g), 3, ctx->acc, 0, ctx->stream), "seed reduction");
   ctx->lam_cur = 0;
   ctx->adj_T = ctx->t;
   ctx->adj_t = ctx->t;
@@ -457,11 +512,9 @@ int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
     int32_t st = forward_state(ctx, s, &P);
     if (st != LBM_OK) return st;
     HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, P, ctx->flags, ctx->has_mask, ctx->force,
-                                 ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->partials, ctx->g, ctx->p,
+                                 ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->adj_acc, ctx->g, ctx->p,
                                  ctx->stream),
             "adjoint sweep launch");
-    HIP_TRY(launch_sum_partials(ctx->partials, num_blocks(ctx->g), 3, ctx->acc, 1, ctx->stream),
-            "adjoint reduction");
     ctx->lam_cur ^= 1;
     ctx->adj_t -= 1;
   }
@@ -479,6 +532,7 @@ int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev, in
                                      ctx->p, ctx->stream),
             "init gradient launch");
   if (dL_dF) {
+    HIP_TRY(launch_sum_partials(ctx->adj_acc, num_blocks(ctx->g), 3, ctx->acc, 0, ctx->stream), "dL/dF reduction");
     HIP_TRY(hipMemcpyAsync(dL_dF, ctx->acc, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "dL/dF copy");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "dL/dF sync");
   }

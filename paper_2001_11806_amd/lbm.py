@@ -37,7 +37,7 @@ class Config(ctypes.Structure):
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("rates", Rates), ("rho0", ctypes.c_double), ("compressible", ctypes.c_int32),
                 ("pattern", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
-                ("max_tape_steps", ctypes.c_int32)]
+                ("max_tape_steps", ctypes.c_int32), ("launch_mode", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -99,7 +99,7 @@ def _check(status):
 
 def make_config(stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0.0, magic=0.0,
                 omega_hi=(1.0, 1.0, 1.0, 1.0), rho0=1.0, compressible=True, pattern=0,
-                checkpoint_every=0, max_tape_steps=0):
+                checkpoint_every=0, max_tape_steps=0, launch_mode=0):
     nx, ny, nz = dims
     cfg = Config()
     cfg.stencil = STENCILS[stencil]
@@ -117,6 +117,7 @@ def make_config(stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0
     cfg.pattern = int(pattern)
     cfg.checkpoint_every = int(checkpoint_every)
     cfg.max_tape_steps = int(max_tape_steps)
+    cfg.launch_mode = int(launch_mode)
     return cfg
 
 
@@ -134,7 +135,8 @@ class LBM:
 
     def __init__(self, stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0.0, magic=0.0,
                  omega_hi=(1.0, 1.0, 1.0, 1.0), rho0=1.0, compressible=True, mask=None,
-                 checkpoint_every=0, max_tape_steps=0, device="cuda:0", stream=None):
+                 checkpoint_every=0, max_tape_steps=0, device="cuda:0", stream=None, pattern=0,
+                 launch_mode=0):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -144,7 +146,7 @@ class LBM:
         self.Q = QS[stencil]
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
         self.cfg = make_config(stencil, method, dtype, dims, omega, omega_bulk, omega_odd, magic, omega_hi,
-                               rho0, compressible, 0, checkpoint_every, max_tape_steps)
+                               rho0, compressible, pattern, checkpoint_every, max_tape_steps, launch_mode)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
