@@ -80,10 +80,10 @@ class Timer:
 
 
 def run_forward(torch, LBM, inputs, stencil, method, dtype, dims, rates, mask, u, F=None, profile=None,
-                steps=100, warmup=10):
+                steps=100, warmup=10, pattern=0):
     lbm = LBM(stencil, method, dtype, dims, rates["omega"], rates.get("omega_bulk", 1.0),
               rates.get("omega_odd", 0.0), rates.get("magic", 0.0), rates.get("omega_hi", (1.0,) * 4),
-              mask=mask)
+              mask=mask, pattern=pattern)
     if F is not None:
         lbm.set_force(F)
     if profile is not None:
@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,copy,c1,c3,c4,c5)")
+    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,aa,copy,c1,c3,c4,c5)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU halo exchange is not built "
@@ -159,6 +159,15 @@ def main():
         r32["rel_l2_u_vs_f64_same_gpu"] = float(d.norm() / u64.double()[:, fl].norm())
         extras["c2_d3q19_trt_256_f32"] = r32
         log("  %.0f MLUPS, rel err u %.2e" % (r32["mlups"], r32["rel_l2_u_vs_f64_same_gpu"]))
+    if want("aa"):
+        log("C2 D3Q19 TRT 256^3 f64, AA pattern (one array)")
+        raa = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f64", (n, n, n), trt, mask, u, F=F,
+                          steps=args.steps, warmup=args.warmup, pattern=1)
+        uaa = raa.pop("u_out")
+        raa["u_equal_to_two_array_run"] = bool(torch.equal(uaa, u64))
+        extras["c2_d3q19_trt_256_f64_aa"] = raa
+        log("  %.0f MLUPS, %.0f GB/s, identical to two-array: %s" % (raa["mlups"], raa["achieved_GBps"],
+                                                                    raa["u_equal_to_two_array_run"]))
     del u64
     torch.cuda.empty_cache()
 

@@ -87,7 +87,9 @@ typedef struct {
   lbm_rates rates;          /* every used rate must lie in (0, 2)                   */
   double rho0;              /* reference density: storage shift and Eq. (3) rho_0  */
   int32_t compressible;     /* 1: rho_0 = rho in Eq. (3) (default); 0: incompressible */
-  int32_t pattern;          /* 0: two-array pull (the only pattern implemented)     */
+  int32_t pattern;          /* 0: two arrays, stream-pull-collide (Sec. IV-B);
+                               1: AA pattern in one array (Sec. IV-B, Fig. "AA update
+                               pattern"): half the memory, no adjoint tape          */
   int32_t checkpoint_every; /* k > 0 enables the adjoint tape (PDF copy every k steps) */
   int32_t max_tape_steps;   /* longest forward run the tape covers (adjoint only)   */
   int32_t launch_mode;      /* 0: automatic -- lattices of at most 64 MiB per grid without a
@@ -97,7 +99,8 @@ typedef struct {
 
 /* Supported combinations: SRT, TRT on all stencils; MRT on D2Q9 and D3Q27;
  * CUMULANT on D2Q9 and D3Q27 with omega_hi all equal to 1, compressible and
- * without body force.  Others return LBM_EUNSUPPORTED. */
+ * without body force; both patterns for every method; the adjoint tape for
+ * compressible SRT with pattern 0.  Others return LBM_EUNSUPPORTED. */
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when
  * checkpoint_every > 0) and copies the solid mask in.

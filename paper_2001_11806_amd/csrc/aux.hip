@@ -15,12 +15,13 @@ bool sweep_supported(int stencil, int method) {
   return false;
 }
 
-hipError_t launch_sweep(int stencil, int method, int dtype, const void* src, void* dst, const uint8_t* flags,
-                        const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s) {
+hipError_t launch_sweep(int stencil, int method, int dtype, int phase, const void* src, void* dst,
+                        const uint8_t* flags, const void* force_y, const Geo& g, const Params& p, int has_mask,
+                        hipStream_t s) {
   switch (stencil) {
-    case 0: return launch_sweep_d2q9(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
-    case 1: return launch_sweep_d3q19(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
-    case 2: return launch_sweep_d3q27(method, dtype, src, dst, flags, force_y, g, p, has_mask, s);
+    case 0: return launch_sweep_d2q9(method, dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case 1: return launch_sweep_d3q19(method, dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case 2: return launch_sweep_d3q27(method, dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
   }
   return hipErrorInvalidValue;
 }
@@ -86,6 +87,58 @@ __device__ __forceinline__ void block_sum(double (&v)[W]) {
   }
 }
 
+
+// --------------------------------------------------------------- layouts
+// Where the post-collision populations P^t(x, q) of the stored state live:
+//   0  two-array pattern: slot (x, q);
+//   1  AA, after an even kernel: slot (x, opp q);
+//   2  AA, after an odd kernel or after initialisation: slot (x + c_q, q),
+//      or (x, opp q) when x + c_q is solid.
+// Solid cells keep their own slots (x, q) in every layout.
+template <class L, class T>
+__device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int has_mask, int layout,
+                                          const CellIdx& c, const Geo& g, double* v) {
+  const size_t N = (size_t)g.N;
+  const bool solid = has_mask && (flags[c.cell] & 1);
+  if (layout == 0 || solid) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + q * N + c.cell);
+  } else if (layout == 1) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + opp<L>(q) * N + c.cell);
+  } else {
+    LBM_NEIGHBOURS(c, g)
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
+      const bool bb = q > 0 && has_mask && (flags[d] & 1);
+      v[q] = (double)Storage<T>::load(bb ? P + opp<L>(q) * N + c.cell : P + q * N + d);
+    }
+  }
+}
+
+template <class L, class T>
+__device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_mask, int layout, const CellIdx& c,
+                                           const Geo& g, const double* v) {
+  const size_t N = (size_t)g.N;
+  const bool solid = has_mask && (flags[c.cell] & 1);
+  if (layout == 0 || solid) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, v[q]);
+  } else if (layout == 1) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) store_from_double(P + opp<L>(q) * N + c.cell, v[q]);
+  } else {
+    LBM_NEIGHBOURS(c, g)
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
+      const bool bb = q > 0 && has_mask && (flags[d] & 1);
+      store_from_double(bb ? P + opp<L>(q) * N + c.cell : P + q * N + d, v[q]);
+    }
+  }
+}
+
 // --------------------------------------------------------------- flags
 // bit 0: solid; bit 1: fluid cell with at least one solid upstream neighbour.
 template <class L>
@@ -114,7 +167,7 @@ hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags,
 // --------------------------------------------------------------- init
 // P = f^eq(rho, u) (Eq. 3, second order), stored shifted by w rho_0.
 template <class L, class T>
-__global__ __launch_bounds__(512) void k_init(T* __restrict__ P, const uint8_t* __restrict__ flags, int has_mask,
+__global__ __launch_bounds__(512) void k_init(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
                                               const void* rho, const void* u, int fdt, Geo g, double rho0,
                                               int compressible) {
   const CellIdx c = cell_of(g);
@@ -130,23 +183,24 @@ __global__ __launch_bounds__(512) void k_init(T* __restrict__ P, const uint8_t* 
   }
   const double rr = compressible ? r : rho0;
   const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+  double v[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
-    double v = 0.0;
+    v[q] = 0.0;
     if (!solid) {
       const double cu = cdot<L>(q, ux, uy, uz);
-      v = weight<L>(q) * ((r - rho0) + rr * (3.0 * cu + 4.5 * cu * cu - usq));
+      v[q] = weight<L>(q) * ((r - rho0) + rr * (3.0 * cu + 4.5 * cu * cu - usq));
     }
-    store_from_double(P + q * N + c.cell, v);
   }
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
 }
 
-hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, const void* rho,
-                       const void* u, int field_dtype, const Geo& g, const Params& p, hipStream_t s) {
+hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
+                       const void* rho, const void* u, int field_dtype, const Geo& g, const Params& p, hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_init<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags, has_mask,
-                         rho, u, field_dtype, g, p.rho0, p.compressible);
+                         layout, rho, u, field_dtype, g, p.rho0, p.compressible);
       return hipGetLastError();
     })
   })
@@ -156,7 +210,7 @@ hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, in
 // Stored state is post-collision: rho = sum f, u = (sum c f - F/2) / rho_0.
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                 int has_mask, const typename Storage<T>::R* __restrict__ force_y,
+                                                 int has_mask, int layout, const typename Storage<T>::R* __restrict__ force_y,
                                                  void* rho_out, void* u_out, int fdt, Geo g, double rho0,
                                                  int compressible) {
   const CellIdx c = cell_of(g);
@@ -164,10 +218,12 @@ __global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const 
   const size_t N = (size_t)g.N;
   double r = 0, ux = 0, uy = 0, uz = 0;
   if (!(has_mask && (flags[c.cell] & 1))) {
+    double f[L::Q];
+    load_post<L, T>(P, flags, has_mask, layout, c, g, f);
     double d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      const double v = (double)Storage<T>::load(P + q * N + c.cell);
+      const double v = f[q];
       d += v;
       jx += L::c(q, 0) * v;
       jy += L::c(q, 1) * v;
@@ -187,14 +243,14 @@ __global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const 
   }
 }
 
-hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
                           const void* force_y, void* rho, void* u, int field_dtype, const Geo& g, const Params& p,
                           hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       using R = typename Storage<T>::R;
       hipLaunchKernelGGL((k_readout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible);
+                         has_mask, layout, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible);
       return hipGetLastError();
     })
   })
@@ -203,16 +259,18 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
 // --------------------------------------------------------------- totals
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_conserved(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                   int has_mask, double* __restrict__ partials, Geo g,
+                                                   int has_mask, int layout, double* __restrict__ partials, Geo g,
                                                    double rho0) {
   const CellIdx c = cell_of(g);
   const size_t N = (size_t)g.N;
   double v[4] = {0, 0, 0, 0};
   if (c.valid && !(has_mask && (flags[c.cell] & 1))) {
+    double pf[L::Q];
+    load_post<L, T>(P, flags, has_mask, layout, c, g, pf);
     double d = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      const double f = (double)Storage<T>::load(P + q * N + c.cell);
+      const double f = pf[q];
       d += f;
       v[1] += L::c(q, 0) * f;
       v[2] += L::c(q, 1) * f;
@@ -243,14 +301,14 @@ hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width
   return hipGetLastError();
 }
 
-hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
                             double* partials, double* out4, const Geo& g, const Params& p, hipStream_t s) {
   hipError_t e = hipSuccess;
   auto body = [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     hipLaunchKernelGGL((k_conserved<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, partials, g, p.rho0);
+                       has_mask, layout, partials, g, p.rho0);
     return hipGetLastError();
   };
   auto by_dtype = [&](auto lat) -> hipError_t {
@@ -274,43 +332,47 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
 
 // --------------------------------------------------------------- PDF I/O
 template <class L, class T>
-__global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, double* __restrict__ out, Geo g,
+__global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                  int has_mask, int layout, double* __restrict__ out, Geo g,
                                                   double rho0) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
+  double v[L::Q];
+  load_post<L, T>(P, flags, has_mask, layout, c, g, v);
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q)
-    out[q * N + c.cell] = (double)Storage<T>::load(P + q * N + c.cell) + weight<L>(q) * rho0;
+  for (int q = 0; q < L::Q; ++q) out[q * N + c.cell] = v[q] + weight<L>(q) * rho0;
 }
 
 template <class L, class T>
-__global__ __launch_bounds__(512) void k_set_pdfs(T* __restrict__ P, const double* __restrict__ in, Geo g,
-                                                  double rho0) {
+__global__ __launch_bounds__(512) void k_set_pdfs(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
+                                                  const double* __restrict__ in, Geo g, double rho0) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
+  double v[L::Q];
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, in[q * N + c.cell] - weight<L>(q) * rho0);
+  for (int q = 0; q < L::Q; ++q) v[q] = in[q * N + c.cell] - weight<L>(q) * rho0;
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
 }
 
-hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, double* out, const Geo& g, const Params& p,
-                           hipStream_t s) {
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
+                           double* out, const Geo& g, const Params& p, hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
-      hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, out, g,
-                         p.rho0);
+      hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                         has_mask, layout, out, g, p.rho0);
       return hipGetLastError();
     })
   })
 }
 
-hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const double* in, const Geo& g, const Params& p,
-                           hipStream_t s) {
+hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
+                           const double* in, const Geo& g, const Params& p, hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
-      hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, in, g,
-                         p.rho0);
+      hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags,
+                         has_mask, layout, in, g, p.rho0);
       return hipGetLastError();
     })
   })

@@ -28,7 +28,8 @@ struct Params {
 inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
 
 // forward
-hipError_t launch_sweep(int stencil, int method, int dtype, const void* src, void* dst,
+// phase -1: two-array sweep src -> dst; 0 / 1: AA even / odd kernel in place on src
+hipError_t launch_sweep(int stencil, int method, int dtype, int phase, const void* src, void* dst,
                         const uint8_t* flags, const void* force_y, const Geo& g, const Params& p,
                         int has_mask, hipStream_t s);
 bool sweep_supported(int stencil, int method);
@@ -36,19 +37,21 @@ bool sweep_supported(int stencil, int method);
 // auxiliary (aux.hip)
 hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, const Geo& g,
                               hipStream_t s);
-hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask,
+// layout of the stored state: 0 two-array; 1 AA after an even kernel;
+// 2 AA streamed (after an odd kernel or initialisation)
+hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
                        const void* rho, const void* u, int field_dtype, const Geo& g,
                        const Params& p, hipStream_t s);
-hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
                           const void* force_y, void* rho, void* u, int field_dtype, const Geo& g,
                           const Params& p, hipStream_t s);
 hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags,
-                            int has_mask, double* partials, double* out4, const Geo& g,
+                            int has_mask, int layout, double* partials, double* out4, const Geo& g,
                             const Params& p, hipStream_t s);
-hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, double* out, const Geo& g,
-                           const Params& p, hipStream_t s);
-hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const double* in, const Geo& g,
-                           const Params& p, hipStream_t s);
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                           int layout, double* out, const Geo& g, const Params& p, hipStream_t s);
+hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
+                           const double* in, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes,
                          hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc,

@@ -117,7 +117,7 @@ int32_t validate(const lbm_config* cfg) {
     for (int i = 0; i < nhi; ++i)
       if (!rate_ok(r.omega_hi[i])) return fail(LBM_EINVAL, "omega_hi[%d] = %g is outside (0, 2)", i, r.omega_hi[i]);
   }
-  if (cfg->pattern != 0) return fail(LBM_EUNSUPPORTED, "only the two-array pull pattern (0) is implemented");
+  if (cfg->pattern != 0 && cfg->pattern != 1) return fail(LBM_EINVAL, "pattern must be 0 (two arrays) or 1 (AA)");
   if (!sweep_supported(cfg->stencil, cfg->method))
     return fail(LBM_EUNSUPPORTED, "method %d is not implemented on stencil %d", cfg->method, cfg->stencil);
   if (cfg->method == LBM_CUMULANT) {
@@ -133,6 +133,7 @@ int32_t validate(const lbm_config* cfg) {
     if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
     if (!adjoint_supported(cfg->stencil, cfg->method) || !cfg->compressible)
       return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT method only");
+    if (cfg->pattern != 0) return fail(LBM_EUNSUPPORTED, "the adjoint needs the two-array pattern");
   }
   return LBM_OK;
 }
@@ -178,9 +179,30 @@ int32_t alloc(void** p, size_t bytes, const char* what) {
 }
 
 int32_t sweep_once(lbm_ctx* c, const void* src, void* dst) {
-  HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, src, dst, c->flags, c->force, c->g, c->p,
+  HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, -1, src, dst, c->flags, c->force, c->g, c->p,
                        c->has_mask, c->stream),
           "sweep launch");
+  return LBM_OK;
+}
+
+bool is_aa(const lbm_ctx* c) { return c->cfg.pattern == 1; }
+
+// Layout of the stored state (see aux.hip): two arrays 0; AA 2 after an even
+// number of steps (streamed), 1 after an odd number (inverted).
+int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
+
+// One forward step on the context's stream.
+int32_t step_once(lbm_ctx* c) {
+  if (is_aa(c)) {
+    HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
+                         c->force, c->g, c->p, c->has_mask, c->stream),
+            "AA sweep launch");
+  } else {
+    int32_t st = sweep_once(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
+    if (st != LBM_OK) return st;
+    c->cur ^= 1;
+  }
+  c->t += 1;
   return LBM_OK;
 }
 
@@ -198,8 +220,12 @@ int32_t ensure_graph(lbm_ctx* c, int parity) {
   int cur = parity;
   hipError_t e = hipSuccess;
   for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) {
-    e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, c->grid[cur], c->grid[cur ^ 1], c->flags,
-                     c->force, c->g, c->p, c->has_mask, c->cap_stream);
+    if (is_aa(c))   // parity = time parity: even / odd kernels alternate on one array
+      e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, cur, c->grid[0], nullptr, c->flags, c->force,
+                       c->g, c->p, c->has_mask, c->cap_stream);
+    else            // parity = current grid
+      e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, -1, c->grid[cur], c->grid[cur ^ 1], c->flags,
+                       c->force, c->g, c->p, c->has_mask, c->cap_stream);
     cur ^= 1;
   }
   hipGraph_t graph = nullptr;
@@ -221,6 +247,7 @@ int32_t ensure_graph(lbm_ctx* c, int parity) {
 // Both grids must hold the same values at solid cells: the sweep never
 // writes them, and lbm_get_pdfs reports them from whichever grid is current.
 int32_t mirror_grid(lbm_ctx* c) {
+  if (is_aa(c)) return LBM_OK;
   HIP_TRY(hipMemcpyAsync(c->grid[1], c->grid[0], c->grid_bytes, hipMemcpyDeviceToDevice, c->stream), "grid mirror");
   return LBM_OK;
 }
@@ -265,7 +292,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
     free_ctx(c);
     return s;
   };
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < (cfg->pattern == 1 ? 1 : 2); ++i)
     if ((st = alloc(&c->grid[i], c->grid_bytes, "PDF grid")) != LBM_OK) return bail(st);
   if ((st = alloc(&c->force, 3 * (size_t)cfg->ny * rb, "force table")) != LBM_OK) return bail(st);
   if ((st = alloc((void**)&c->partials, (size_t)nblk * 4 * sizeof(double), "reduction partials")) != LBM_OK)
@@ -299,8 +326,8 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
     (void)hipFree(solid_dev);
     if (e != hipSuccess) return bail(hip_fail(e, "solid mask upload"));
   }
-  if ((e = launch_init(cfg->stencil, cfg->dtype, c->grid[0], c->flags, c->has_mask, nullptr, nullptr, LBM_F64, c->g,
-                       c->p, c->stream)) != hipSuccess)
+  if ((e = launch_init(cfg->stencil, cfg->dtype, c->grid[0], c->flags, c->has_mask, cfg->pattern == 1 ? 2 : 0,
+                       nullptr, nullptr, LBM_F64, c->g, c->p, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "initial state"));
   if ((st = mirror_grid(c)) != LBM_OK) return bail(st);
   reset_time(c);
@@ -360,8 +387,9 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
   int32_t st = check_field_dtype(field_dtype);
   if (st != LBM_OK) return st;
   ctx->cur = 0;
-  HIP_TRY(launch_init(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, rho_dev, u_dev,
-                      field_dtype, ctx->g, ctx->p, ctx->stream),
+  ctx->t = 0;
+  HIP_TRY(launch_init(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, layout_of(ctx),
+                      rho_dev, u_dev, field_dtype, ctx->g, ctx->p, ctx->stream),
           "init launch");
   int32_t ms = mirror_grid(ctx);
   if (ms != LBM_OK) return ms;
@@ -379,9 +407,10 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
   int32_t i = 0;
   if (graph_replay(ctx)) {
     for (; n - i >= kGraphSteps; i += kGraphSteps) {
-      int32_t st = ensure_graph(ctx, ctx->cur);
+      const int key = is_aa(ctx) ? (int)(ctx->t & 1) : ctx->cur;
+      int32_t st = ensure_graph(ctx, key);
       if (st != LBM_OK) return st;
-      HIP_TRY(hipGraphLaunch(ctx->graph_exec[ctx->cur], ctx->stream), "graph launch");
+      HIP_TRY(hipGraphLaunch(ctx->graph_exec[key], ctx->stream), "graph launch");
       ctx->t += kGraphSteps;
     }
   }
@@ -391,10 +420,8 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
       HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
               "tape copy");
     }
-    int32_t st = sweep_once(ctx, ctx->grid[ctx->cur], ctx->grid[ctx->cur ^ 1]);
+    int32_t st = step_once(ctx);
     if (st != LBM_OK) return st;
-    ctx->cur ^= 1;
-    ctx->t += 1;
   }
   ctx->adj_t = -1;
   return LBM_OK;
@@ -411,7 +438,8 @@ int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t fi
   int32_t st = check_field_dtype(field_dtype);
   if (st != LBM_OK) return st;
   if (!rho_dev && !u_dev) return LBM_OK;
-  HIP_TRY(launch_readout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask, ctx->force,
+  HIP_TRY(launch_readout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+                         layout_of(ctx), ctx->force,
                          rho_dev, u_dev, field_dtype, ctx->g, ctx->p, ctx->stream),
           "readout launch");
   return LBM_OK;
@@ -420,7 +448,7 @@ int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t fi
 int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
   if (!ctx || !out) return fail(LBM_EINVAL, "NULL argument");
   HIP_TRY(launch_conserved(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
-                           ctx->partials, ctx->acc + 4, ctx->g, ctx->p, ctx->stream),
+                           layout_of(ctx), ctx->partials, ctx->acc + 4, ctx->g, ctx->p, ctx->stream),
           "conservation launch");
   HIP_TRY(hipMemcpyAsync(out, ctx->acc + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "totals copy");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "totals sync");
@@ -431,8 +459,8 @@ int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
 
 int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev) {
   if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
-  HIP_TRY(launch_get_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], pdfs_dev, ctx->g, ctx->p,
-                          ctx->stream),
+  HIP_TRY(launch_get_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+                          layout_of(ctx), pdfs_dev, ctx->g, ctx->p, ctx->stream),
           "get_pdfs launch");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "get_pdfs sync");
   return LBM_OK;
@@ -442,7 +470,9 @@ int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev) {
   if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
   if (ctx->k > 0) return fail(LBM_ESTATE, "set_pdfs is not available with the adjoint tape (no initial fields)");
   ctx->cur = 0;
-  HIP_TRY(launch_set_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], pdfs_dev, ctx->g, ctx->p, ctx->stream),
+  ctx->t = 0;
+  HIP_TRY(launch_set_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, layout_of(ctx),
+                          pdfs_dev, ctx->g, ctx->p, ctx->stream),
           "set_pdfs launch");
   int32_t ms = mirror_grid(ctx);
   if (ms != LBM_OK) return ms;

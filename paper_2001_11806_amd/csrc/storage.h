@@ -11,6 +11,15 @@
 
 namespace lbm {
 
+// Materialise an FP32 value before it is rounded to a 16-bit type, so the
+// compiler cannot fuse the last FMA with the conversion in some kernels and
+// not in others: every kernel then rounds the same FP32 value once more, and
+// the two-array and AA sweeps stay bit-identical.
+__device__ __forceinline__ float pin_f32(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <class T>
 struct Storage;
 
@@ -37,8 +46,10 @@ struct Storage<__bf16> {
   using R = float;
   static constexpr int code = 2;
   __device__ static R load(const __bf16* p) { return static_cast<float>(*p); }
-  __device__ static void store(__bf16* p, R v) { *p = static_cast<__bf16>(v); }
-  __device__ static void store_nt(__bf16* p, R v) { __builtin_nontemporal_store(static_cast<__bf16>(v), p); }
+  __device__ static void store(__bf16* p, R v) { *p = static_cast<__bf16>(pin_f32(v)); }
+  __device__ static void store_nt(__bf16* p, R v) {
+    __builtin_nontemporal_store(static_cast<__bf16>(pin_f32(v)), p);
+  }
 };
 
 template <>
@@ -46,8 +57,10 @@ struct Storage<_Float16> {
   using R = float;
   static constexpr int code = 3;
   __device__ static R load(const _Float16* p) { return static_cast<float>(*p); }
-  __device__ static void store(_Float16* p, R v) { *p = static_cast<_Float16>(v); }
-  __device__ static void store_nt(_Float16* p, R v) { __builtin_nontemporal_store(static_cast<_Float16>(v), p); }
+  __device__ static void store(_Float16* p, R v) { *p = static_cast<_Float16>(pin_f32(v)); }
+  __device__ static void store_nt(_Float16* p, R v) {
+    __builtin_nontemporal_store(static_cast<_Float16>(pin_f32(v)), p);
+  }
 };
 
 }  // namespace lbm

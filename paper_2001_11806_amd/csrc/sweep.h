@@ -174,39 +174,148 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
   store_cell<T, NT>(dst, c, g, f, L::Q);
 }
 
+// ------------------------------------------------------------------ AA
+// Single-array AA pattern (Sec. IV-B, Fig. "AA update pattern"), two kernels
+// run alternately.  With P^t the post-collision state of step t:
+//   even kernel (t even -> t+1): the array holds the streamed populations,
+//     A[x][q] = g_q(x); collide in place and store inverted, A[x][opp q] = f*_q(x);
+//   odd kernel (t odd -> t+1): pull g_q(x) = A[x - c_q][opp q] (bounce-back:
+//     A[x][q] when x - c_q is solid), collide, push f*_q to A[x + c_q][q]
+//     (bounce-back: A[x][opp q] when x + c_q is solid).
+// In the odd kernel every slot is read and written by the same cell, so the
+// update is race-free in place.  Both kernels move 2 Q s bytes per cell.
+template <class L, class T>
+__device__ __forceinline__ T* plane_row(T* A, int plane, int dir, const CellIdx& c, int ym, int yp, int zm, int zp,
+                                        const Geo& g) {
+  const int cy = L::c(dir, 1), cz = L::c(dir, 2);
+  const int sy = cy > 0 ? ym : (cy < 0 ? yp : c.y);
+  const int sz = cz > 0 ? zm : (cz < 0 ? zp : c.z);
+  return A + (size_t)plane * (size_t)g.N + (size_t)(sz * g.ny + sy) * (size_t)g.nx;
+}
+
+template <class T, int NT>
+__device__ __forceinline__ void put(T* p, typename Storage<T>::R v) {
+  if (NT)
+    Storage<T>::store_nt(p, v);
+  else
+    Storage<T>::store(p, v);
+}
+
+template <class L, int M, class T, int NT>
+__global__ __launch_bounds__(512) void k_sweep_aa_even(T* A, const uint8_t* __restrict__ flags,
+                                                       const typename Storage<T>::R* __restrict__ force_y, Geo g,
+                                                       CollideParams<typename Storage<T>::R> p, int has_mask) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  if (has_mask && (flags[c.cell] & 1)) return;
+  T* row = A + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+  const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(T);
+  R f[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(at_bytes(row + (size_t)q * (size_t)g.N, ox));
+  const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
+  collide<L, M>(f, F, p);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) put<T, NT>(at_bytes(row + (size_t)opp<L>(q) * (size_t)g.N, ox), f[q]);
+}
+
+template <class L, int M, class T, int NT>
+__global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __restrict__ flags,
+                                                      const typename Storage<T>::R* __restrict__ force_y, Geo g,
+                                                      CollideParams<typename Storage<T>::R> p, int has_mask) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  int fl = 0;
+  if (has_mask) {
+    fl = flags[c.cell];
+    if (fl & 1) return;
+  }
+  LBM_NEIGHBOURS(c, g)
+  const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(T), (uint32_t)c.x * (uint32_t)sizeof(T),
+                          (uint32_t)xm * (uint32_t)sizeof(T)};  // x - c_x for c_x = -1, 0, +1
+  R f[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    f[q] = Storage<T>::load(at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]));
+  if (fl & 2) {
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q)
+      if (flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] & 1)
+        f[q] = Storage<T>::load(A + (size_t)q * (size_t)g.N + c.cell);
+  }
+  const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
+  collide<L, M>(f, F, p);
+  if (!(fl & 2)) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+      put<T, NT>(at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]), f[q]);
+  } else {
+    // next to a wall: links into solid cells bounce back into the cell's own
+    // opposite slot; solid cells' slots are never written
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      if (q > 0 && (flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] & 1))
+        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, f[q]);
+      else
+        put<T, NT>(at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]),
+                   f[q]);
+    }
+  }
+}
+
+// phase -1: two-array sweep src -> dst; phase 0 / 1: AA even / odd kernel on src.
 template <class L, int M, class T>
-hipError_t run_sweep(const void* src, void* dst, const uint8_t* flags, const void* force_y, const Geo& g,
+hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags, const void* force_y, const Geo& g,
                      const Params& p, int has_mask, hipStream_t s) {
   using R = typename Storage<T>::R;
   const CollideParams<R> cp = to_collide_params<R>(p);
-  // non-temporal stores once the two grids clearly exceed the on-chip caches
+  // non-temporal stores once the grid clearly exceeds the on-chip caches
   const bool nt = (size_t)g.N * L::Q * sizeof(T) > (size_t(512) << 20);
-  if (nt)
-    hipLaunchKernelGGL((k_sweep<L, M, T, 1>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
-                       (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
-  else
-    hipLaunchKernelGGL((k_sweep<L, M, T, 0>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)src,
-                       (T*)dst, flags, (const R*)force_y, g, cp, has_mask);
+  const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
+  if (phase < 0) {
+    if (nt)
+      hipLaunchKernelGGL((k_sweep<L, M, T, 1>), grid, block, 0, s, (const T*)src, (T*)dst, flags, (const R*)force_y,
+                         g, cp, has_mask);
+    else
+      hipLaunchKernelGGL((k_sweep<L, M, T, 0>), grid, block, 0, s, (const T*)src, (T*)dst, flags, (const R*)force_y,
+                         g, cp, has_mask);
+  } else if (phase == 0) {
+    if (nt)
+      hipLaunchKernelGGL((k_sweep_aa_even<L, M, T, 1>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
+                         has_mask);
+    else
+      hipLaunchKernelGGL((k_sweep_aa_even<L, M, T, 0>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
+                         has_mask);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((k_sweep_aa_odd<L, M, T, 1>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
+                         has_mask);
+    else
+      hipLaunchKernelGGL((k_sweep_aa_odd<L, M, T, 0>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
+                         has_mask);
+  }
   return hipGetLastError();
 }
 
 template <class L, int M>
-hipError_t sweep_for_dtype(int dtype, const void* src, void* dst, const uint8_t* flags, const void* force_y,
-                           const Geo& g, const Params& p, int has_mask, hipStream_t s) {
+hipError_t sweep_for_dtype(int dtype, int phase, const void* src, void* dst, const uint8_t* flags,
+                           const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s) {
   switch (dtype) {
-    case 0: return run_sweep<L, M, double>(src, dst, flags, force_y, g, p, has_mask, s);
-    case 1: return run_sweep<L, M, float>(src, dst, flags, force_y, g, p, has_mask, s);
-    case 2: return run_sweep<L, M, __bf16>(src, dst, flags, force_y, g, p, has_mask, s);
-    case 3: return run_sweep<L, M, _Float16>(src, dst, flags, force_y, g, p, has_mask, s);
+    case 0: return run_sweep<L, M, double>(phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case 1: return run_sweep<L, M, float>(phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case 2: return run_sweep<L, M, __bf16>(phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case 3: return run_sweep<L, M, _Float16>(phase, src, dst, flags, force_y, g, p, has_mask, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_d2q9(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+hipError_t launch_sweep_d2q9(int method, int dtype, int phase, const void* src, void* dst, const uint8_t* flags,
                              const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
-hipError_t launch_sweep_d3q19(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+hipError_t launch_sweep_d3q19(int method, int dtype, int phase, const void* src, void* dst, const uint8_t* flags,
                               const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
-hipError_t launch_sweep_d3q27(int method, int dtype, const void* src, void* dst, const uint8_t* flags,
+hipError_t launch_sweep_d3q27(int method, int dtype, int phase, const void* src, void* dst, const uint8_t* flags,
                               const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s);
 
 }  // namespace lbm

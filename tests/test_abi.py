@@ -77,7 +77,9 @@ def _create(lib, **kw):
     (dict(method="CUMULANT"), B.EUNSUPPORTED, "not implemented"),
     (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 1.2, 1, 1)), B.EUNSUPPORTED, "equal to 1"),
     (dict(method="CUMULANT", stencil="D3Q27", compressible=False), B.EUNSUPPORTED, "compressible"),
-    (dict(pattern=1), B.EUNSUPPORTED, "two-array"),
+    (dict(pattern=2), B.EINVAL, "pattern"),
+    (dict(pattern=1, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "two-array pattern"),
+    (dict(launch_mode=3), B.EINVAL, "launch_mode"),
     (dict(method="TRT", magic=3 / 16, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
     (dict(checkpoint_every=5, max_tape_steps=0), B.EINVAL, "max_tape_steps"),
     (dict(checkpoint_every=-1), B.EINVAL, "checkpoint_every"),
