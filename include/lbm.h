@@ -97,7 +97,8 @@ typedef struct {
                                dominates there); 1: one direct launch per step      */
 } lbm_config;
 
-/* Supported combinations: SRT, TRT on all stencils; MRT on D2Q9 and D3Q27;
+/* Supported combinations: SRT, TRT, MRT on all stencils (MRT rates: orders
+ * 3..6 on D3Q27, orders 3 and 4 on D2Q9 and D3Q19);
  * CUMULANT on D2Q9 and D3Q27 with omega_hi all equal to 1, compressible and
  * without body force; both patterns for every method; the adjoint tape for
  * compressible SRT with pattern 0.  Others return LBM_EUNSUPPORTED. */

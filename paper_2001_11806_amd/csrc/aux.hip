@@ -10,8 +10,8 @@ namespace lbm {
 
 // --------------------------------------------------------------- dispatch
 bool sweep_supported(int stencil, int method) {
-  if (method == M_SRT || method == M_TRT) return stencil >= 0 && stencil <= 2;
-  if (method == M_MRT || method == M_CUMULANT) return stencil == 0 || stencil == 2;
+  if (method == M_SRT || method == M_TRT || method == M_MRT) return stencil >= 0 && stencil <= 2;
+  if (method == M_CUMULANT) return stencil == 0 || stencil == 2;
   return false;
 }
 

@@ -276,6 +276,141 @@ __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParam
       }
 }
 
+// ---------------------------------------------------------------- MRT (general stencil)
+// Eq. (4) with the weighted-orthogonal basis built exactly as Sec. III-A/C
+// describe it: independent monomials x^a y^b z^c (a, b, c <= 2, rows that
+// vanish on the stencil dropped), second order split into shear (x^2 - y^2,
+// x^2 - z^2, off-diagonal) and bulk (x^2 + y^2 + z^2), ordered by order, then
+// Gram-Schmidt with <p, r>_w = sum_q w_q p(c_q) r(c_q).  The basis is computed
+// at compile time (constexpr), so every matrix entry is an immediate and the
+// zero entries cost nothing.  Used for D3Q19, whose basis is not a tensor
+// product.
+template <int Q>
+struct MrtBasis {
+  double m[Q][Q];      // row k: polynomial k evaluated on the directions
+  double inv_norm[Q];  // 1 / sum_q w_q m[k][q]^2
+  int group[Q];        // 0 conserved, 1 shear, 2 bulk, n >= 3: order n
+};
+
+__host__ __device__ constexpr double ipow(int v, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= v;
+  return r;
+}
+
+template <class L>
+__host__ __device__ constexpr double mono(int q, int a, int b, int c) {
+  return ipow(L::c(q, 0), a) * ipow(L::c(q, 1), b) * ipow(L::c(q, 2), c);
+}
+
+template <class L>
+__host__ __device__ constexpr MrtBasis<L::Q> make_mrt_basis() {
+  MrtBasis<L::Q> B{};
+  double raw[L::Q][L::Q] = {};
+  int n = 0;
+  auto add_mono = [&](int a, int b, int c, int grp) {
+    bool any = false;
+    for (int q = 0; q < L::Q; ++q) any = any || mono<L>(q, a, b, c) != 0.0;
+    if (!any || n >= L::Q) return;
+    for (int q = 0; q < L::Q; ++q) raw[n][q] = mono<L>(q, a, b, c);
+    B.group[n++] = grp;
+  };
+  add_mono(0, 0, 0, 0);
+  add_mono(1, 0, 0, 0);
+  add_mono(0, 1, 0, 0);
+  if (L::DIM == 3) add_mono(0, 0, 1, 0);
+  // second order: shear differences and off-diagonals, then bulk
+  for (int k = 1; k < L::DIM; ++k) {
+    for (int q = 0; q < L::Q; ++q) raw[n][q] = mono<L>(q, 2, 0, 0) - (k == 1 ? mono<L>(q, 0, 2, 0) : mono<L>(q, 0, 0, 2));
+    B.group[n++] = 1;
+  }
+  add_mono(1, 1, 0, 1);
+  if (L::DIM == 3) {
+    add_mono(1, 0, 1, 1);
+    add_mono(0, 1, 1, 1);
+  }
+  for (int q = 0; q < L::Q; ++q)
+    raw[n][q] = mono<L>(q, 2, 0, 0) + mono<L>(q, 0, 2, 0) + (L::DIM == 3 ? mono<L>(q, 0, 0, 2) : 0.0);
+  B.group[n++] = 2;
+  for (int order = 3; order <= 2 * L::DIM; ++order)
+    for (int a = 0; a <= 2; ++a)
+      for (int b = 0; b <= 2; ++b)
+        for (int c = 0; c <= (L::DIM == 3 ? 2 : 0); ++c)
+          if (a + b + c == order) add_mono(a, b, c, order);
+  // weighted Gram-Schmidt
+  for (int k = 0; k < L::Q; ++k) {
+    for (int j = 0; j < k; ++j) {
+      double num = 0.0, den = 0.0;
+      for (int q = 0; q < L::Q; ++q) {
+        num += weight<L>(q) * raw[k][q] * raw[j][q];
+        den += weight<L>(q) * raw[j][q] * raw[j][q];
+      }
+      for (int q = 0; q < L::Q; ++q) raw[k][q] -= num / den * raw[j][q];
+    }
+  }
+  for (int k = 0; k < L::Q; ++k) {
+    double nrm = 0.0;
+    for (int q = 0; q < L::Q; ++q) {
+      // snap roundoff of exactly-zero entries so they fold away
+      const double v = raw[k][q];
+      B.m[k][q] = (v < 1e-13 && v > -1e-13) ? 0.0 : v;
+      nrm += weight<L>(q) * B.m[k][q] * B.m[k][q];
+    }
+    B.inv_norm[k] = 1.0 / nrm;
+  }
+  return B;
+}
+
+template <class L, class R>
+__device__ __forceinline__ void collide_mrt_gs(R* f, const R* F, const CollideParams<R>& p) {
+  constexpr MrtBasis<L::Q> B = make_mrt_basis<L>();
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (jx + R(0.5) * F[0]) * inv, uy = (jy + R(0.5) * F[1]) * inv,
+          uz = (jz + R(0.5) * F[2]) * inv;
+  const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF3 = R(3) * (ux * F[0] + uy * F[1] + uz * F[2]);
+  R neq[L::Q], src[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R w = R(weight<L>(q));
+    const R cu = cdot<L>(q, ux, uy, uz);
+    const R cF = cdot<L>(q, F[0], F[1], F[2]);
+    neq[q] = f[q] - w * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));
+    src[q] = w * (R(3) * cF - uF3 + R(9) * cu * cF);
+  }
+  R gam[L::Q];
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    const int grp = B.group[k];
+    R a = R(0), b = R(0);
+    if (grp != 0) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q)
+        if (B.m[k][q] != 0.0) a += R(B.m[k][q]) * neq[q];
+    }
+    // the Guo source has no component of order >= 3
+    if (k > 0 && grp <= 2) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q)
+        if (B.m[k][q] != 0.0) b += R(B.m[k][q]) * src[q];
+    }
+    const R rate = grp == 0 ? R(0) : (grp == 1 ? p.om : (grp == 2 ? p.om_b : p.hi[grp - 3]));
+    gam[k] = (-rate * a + (R(1) - R(0.5) * rate) * b) * R(B.inv_norm[k]);
+  }
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    R d = R(0);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k)
+      if (B.m[k][q] != 0.0) d += R(B.m[k][q]) * gam[k];
+    f[q] += R(weight<L>(q)) * d;
+  }
+}
+
 // ---------------------------------------------------------------- cumulant
 // Cumulant collision (Eq. 9, Sec. III-B) for the case where every rate of
 // order >= 3 is 1.  Then all post-collision cumulants of order >= 3 vanish:
@@ -427,6 +562,7 @@ template <class L, int M, class R>
 __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>& p) {
   if constexpr (M == M_SRT) collide_srt<L>(f, F, p);
   else if constexpr (M == M_TRT) collide_trt<L>(f, F, p);
+  else if constexpr (M == M_MRT && L::Q == 19) collide_mrt_gs<L>(f, F, p);
   else if constexpr (M == M_MRT) collide_mrt<L>(f, F, p);
   else collide_cumulant<L>(f, F, p);
 }

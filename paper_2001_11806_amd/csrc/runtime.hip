@@ -113,7 +113,7 @@ int32_t validate(const lbm_config* cfg) {
   }
   if (cfg->method == LBM_MRT || cfg->method == LBM_CUMULANT) {
     if (!rate_ok(r.omega_bulk)) return fail(LBM_EINVAL, "omega_bulk = %g is outside (0, 2)", r.omega_bulk);
-    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
+    const int nhi = cfg->stencil == LBM_D3Q27 ? 4 : 2;   // highest moment order 2 DIM, or 4 on D3Q19
     for (int i = 0; i < nhi; ++i)
       if (!rate_ok(r.omega_hi[i])) return fail(LBM_EINVAL, "omega_hi[%d] = %g is outside (0, 2)", i, r.omega_hi[i]);
   }

@@ -73,7 +73,7 @@ def _create(lib, **kw):
     (dict(method="TRT", omega_odd=2.5), B.EINVAL, "omega_odd"),
     (dict(method="MRT", omega_bulk=2.2), B.EINVAL, "omega_bulk"),
     (dict(method="MRT", stencil="D3Q27", omega_hi=(1, 1, 2.0, 1)), B.EINVAL, "omega_hi"),
-    (dict(method="MRT"), B.EUNSUPPORTED, "not implemented"),
+    (dict(method="MRT", omega_hi=(1, 2.5, 1, 1)), B.EINVAL, "omega_hi[1]"),
     (dict(method="CUMULANT"), B.EUNSUPPORTED, "not implemented"),
     (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 1.2, 1, 1)), B.EUNSUPPORTED, "equal to 1"),
     (dict(method="CUMULANT", stencil="D3Q27", compressible=False), B.EUNSUPPORTED, "compressible"),

@@ -19,7 +19,7 @@ from oracle import run as orun
 pytestmark = pytest.mark.gpu
 
 COMBOS = [("D2Q9", "SRT"), ("D2Q9", "TRT"), ("D2Q9", "MRT"), ("D2Q9", "CUMULANT"),
-          ("D3Q19", "SRT"), ("D3Q19", "TRT"),
+          ("D3Q19", "SRT"), ("D3Q19", "TRT"), ("D3Q19", "MRT"),
           ("D3Q27", "SRT"), ("D3Q27", "TRT"), ("D3Q27", "MRT"), ("D3Q27", "CUMULANT")]
 DTYPES = ["f64", "f32", "bf16", "f16"]
 MRT_RATES = dict(RATES, omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.1, 0.9, 1.3, 1.05))
