@@ -77,6 +77,10 @@ typedef struct {
   double omega_odd;   /* TRT odd rate; if <= 0 it is derived from `magic`          */
   double magic;       /* TRT Lambda = (1/omega_even - 1/2)(1/omega_odd - 1/2)      */
   double omega_hi[4]; /* MRT/cumulant rates of moment orders 3, 4, 5, 6            */
+  double cs_smag;     /* Smagorinsky constant C_S (Sec. III-C "Turbulence models");
+                         > 0 makes the SRT rate / MRT shear rate local:
+                         omega = 2 / (tau0 + sqrt(tau0^2 + 18 C_S^2 P / rho)),
+                         P = sqrt(2 Pi^neq : Pi^neq), tau0 = 1 / omega.  0 = off  */
 } lbm_rates;
 
 typedef struct {

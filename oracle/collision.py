@@ -9,6 +9,8 @@ Rates are passed as a plain dict with keys
     omega_odd   TRT odd rate (<= 0: derived from ``magic``)
     magic       TRT parameter Lambda = (1/omega_e - 1/2)(1/omega_o - 1/2)
     omega_hi    MRT/cumulant rates of the moment orders 3, 4, 5, 6
+    cs_smag     Smagorinsky constant C_S (optional; > 0 makes the SRT rate and
+                the MRT shear rate local)
 """
 
 import functools
@@ -29,11 +31,39 @@ def trt_odd_rate(rates):
     return 1.0 / (rates["magic"] / (1.0 / we - 0.5) + 0.5)
 
 
+def nonequilibrium_stress(lat, f, feq):
+    """Pi^neq_ab = sum_q c_qa c_qb (f_q - f^eq_q) (Sec. III-C, Eq. 13);
+    returns an array (3, 3, ...)."""
+    c = lat.c.astype(np.float64)
+    d = f - feq
+    return np.einsum("qa,qb,q...->ab...", c, c, d)
+
+
+def smagorinsky_rate(lat, f, feq, rho, omega0, cs):
+    """Local relaxation rate of the Smagorinsky model (Sec. III-C, Eqs. 11-14).
+
+    nu = nu_0 + (C_S Delta)^2 |S| with Delta = 1, |S| = sqrt(2 S:S),
+    S = -3 omega / (2 rho) Pi^neq and omega = 2 / (6 nu + 1).  With
+    P = sqrt(2 Pi^neq : Pi^neq) this is the quadratic
+    (9 C_S^2 P / rho) omega^2 + 2 tau_0 omega - 2 = 0 (tau_0 = 1 / omega_0),
+    whose positive root is returned.
+    """
+    Pi = nonequilibrium_stress(lat, f, feq)
+    P = np.sqrt(2.0 * (Pi * Pi).sum(axis=(0, 1)))
+    tau0 = 1.0 / omega0
+    a = 9.0 * cs * cs * P / rho
+    disc = np.sqrt(tau0 * tau0 + 2.0 * a)
+    return np.where(a > 0, (disc - tau0) / np.where(a > 0, a, 1.0), 1.0 / tau0)
+
+
 def srt(lat, f, rates, force=None, rho0=1.0, compressible=True):
-    """Eq. (1): f* = f - omega (f - f^eq), plus Guo's (1 - omega/2) S."""
+    """Eq. (1): f* = f - omega (f - f^eq), plus Guo's (1 - omega/2) S; with
+    C_S > 0 omega is the local Smagorinsky rate."""
     om = rates["omega"]
     rho, u = macroscopic(lat, f, force, rho0, compressible)
     feq = equilibrium(lat, rho, u, rho0, compressible)
+    if rates.get("cs_smag", 0.0) > 0.0:
+        om = smagorinsky_rate(lat, f, feq, rho, om, rates["cs_smag"])
     out = f - om * (f - feq)
     if force is not None:
         out = out + (1.0 - 0.5 * om) * guo_source(lat, u, force)
@@ -113,7 +143,8 @@ def _mrt_tables(name):
 
 
 def mrt(lat, f, rates, force=None, rho0=1.0, compressible=True):
-    """Eq. (4) with the weighted-orthogonal basis of ``moments``.
+    """Eq. (4) with the weighted-orthogonal basis of ``moments`` (with C_S > 0
+    the shear rate is the local Smagorinsky rate).
 
     m = M f, m^eq = M f^eq (Eq. 3), f* = f - M^-1 S (m - m^eq); the Guo
     source enters in moment space as M^-1 (I - S/2) M S.  Conserved moments
@@ -121,16 +152,21 @@ def mrt(lat, f, rates, force=None, rho0=1.0, compressible=True):
     their rate does not change the result.
     """
     M, groups, Minv = _mrt_tables(lat.name)
-    s = _group_rates(groups, rates)
     shp = f.shape
     rho, u = macroscopic(lat, f, force, rho0, compressible)
     feq = equilibrium(lat, rho, u, rho0, compressible)
     f2 = f.reshape(lat.Q, -1)
+    s = np.repeat(_group_rates(groups, rates)[:, None], f2.shape[1], axis=1)
+    if rates.get("cs_smag", 0.0) > 0.0:
+        om = smagorinsky_rate(lat, f, feq, rho, rates["omega"], rates["cs_smag"]).reshape(-1)
+        for k, g in enumerate(groups):
+            if g == "shear":
+                s[k] = om
     neq = M @ (f2 - feq.reshape(lat.Q, -1))
-    out = f2 - Minv @ (s[:, None] * neq)
+    out = f2 - Minv @ (s * neq)
     if force is not None:
         S = guo_source(lat, u, force).reshape(lat.Q, -1)
-        out = out + Minv @ ((1.0 - 0.5 * s)[:, None] * (M @ S))
+        out = out + Minv @ ((1.0 - 0.5 * s) * (M @ S))
     return out.reshape(shp)
 
 

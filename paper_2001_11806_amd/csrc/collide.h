@@ -14,7 +14,9 @@
 
 namespace lbm {
 
-enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3 };
+// Internal method codes: the ABI's four, plus SRT and MRT with the
+// Smagorinsky model (local shear rate).
+enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5 };
 
 template <class R>
 struct CollideParams {
@@ -23,8 +25,26 @@ struct CollideParams {
   R om_b;     // bulk
   R om_o;     // TRT odd
   R hi[4];    // orders 3..6
+  R smag18;   // 18 C_S^2
   int compressible;
 };
+
+// Smagorinsky model (Sec. III-C "Turbulence models", Eqs. 11-14): eddy
+// viscosity (C_S Delta)^2 |S| with Delta = 1 and the strain rate from the
+// non-equilibrium stress, S = -3 omega / (2 rho) Pi^neq (Eq. 12).  Inserting
+// |S| into omega = 2 / (6 C_S^2 |S| + 6 nu_0 + 1) (Eq. 14) gives a quadratic
+// in omega whose positive root is
+//   omega = 2 / (tau0 + sqrt(tau0^2 + 18 C_S^2 P / rho)),
+// P = sqrt(2 Pi^neq : Pi^neq), tau0 = 1 / omega_0.  Arguments: the six
+// independent components of Pi^neq.
+template <class R>
+__device__ __forceinline__ R smagorinsky_omega(R xx, R yy, R zz, R xy, R xz, R yz, R rho,
+                                               const CollideParams<R>& p) {
+  const R PP = xx * xx + yy * yy + zz * zz + R(2) * (xy * xy + xz * xz + yz * yz);
+  const R P = sqrt(R(2) * PP);
+  const R tau0 = R(1) / p.om;
+  return R(2) / (tau0 + sqrt(tau0 * tau0 + p.smag18 * P / rho));
+}
 
 // c_q . (x, y, z) with the constant components folded away.
 template <class L, class R>
@@ -56,7 +76,7 @@ __device__ __forceinline__ void density_momentum(const R* f, R& drho, R& jx, R& 
 
 // ---------------------------------------------------------------- SRT
 // Eq. (1): f* = f - omega (f - f^eq) + (1 - omega/2) S, f^eq from Eq. (3).
-template <class L, class R>
+template <class L, class R, bool SMAG = false>
 __device__ __forceinline__ void collide_srt(R* f, const R* F, const CollideParams<R>& p) {
   R drho, jx, jy, jz;
   density_momentum<L>(f, drho, jx, jy, jz);
@@ -67,7 +87,27 @@ __device__ __forceinline__ void collide_srt(R* f, const R* F, const CollideParam
           uz = (jz + R(0.5) * F[2]) * inv;
   const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
   const R uF3 = R(3) * (ux * F[0] + uy * F[1] + uz * F[2]);
-  const R om = p.om, fs = R(1) - R(0.5) * p.om;
+  R om = p.om;
+  if constexpr (SMAG) {
+    R xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const R cu = cdot<L>(q, ux, uy, uz);
+      const R d = f[q] - R(weight<L>(q)) * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));
+      const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+      if (cx != 0) xx += d;
+      if (cy != 0) yy += d;
+      if (cz != 0) zz += d;
+      if (cx * cy == 1) xy += d;
+      if (cx * cy == -1) xy -= d;
+      if (cx * cz == 1) xz += d;
+      if (cx * cz == -1) xz -= d;
+      if (cy * cz == 1) yz += d;
+      if (cy * cz == -1) yz -= d;
+    }
+    om = smagorinsky_omega(xx, yy, zz, xy, xz, yz, rho, p);
+  }
+  const R fs = R(1) - R(0.5) * om;
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     const R w = R(weight<L>(q));
@@ -133,7 +173,7 @@ __device__ __forceinline__ void collide_trt(R* f, const R* F, const CollideParam
 // Groups: order 0, 1 conserved; order 2 split into shear (off-diagonal and
 // traceless diagonal, omega) and bulk (trace, omega_b); order n >= 3 hi[n-3].
 // Eq. (3) has no component of order >= 3 on these stencils.
-template <class L, class R>
+template <class L, class R, bool SMAG = false>
 __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParams<R>& p) {
   constexpr int D = L::DIM;
   constexpr int NK = (D == 3) ? 3 : 1;
@@ -182,7 +222,22 @@ __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParam
   const R ux = (a[1][0][0] + R(0.5) * F[0]) * inv;
   const R uy = (a[0][1][0] + R(0.5) * F[1]) * inv;
   const R uz = (D == 3) ? (a[0][0][NK > 1 ? 1 : 0] + R(0.5) * F[2]) * inv : R(0);
-  const R om = p.om, omb = p.om_b;
+  R om = p.om;
+  if constexpr (SMAG) {
+    // Pi^neq from the Hermite coefficients: off-diagonal A_ab - rr u_a u_b,
+    // diagonal (A_aa - 3 rr u_a^2) / 3 (the neq mass is zero)
+    const R xy = a[1][1][0] - rr * ux * uy;
+    const R xx = (a[2][0][0] - R(3) * rr * ux * ux) * R(1.0 / 3.0);
+    const R yy = (a[0][2][0] - R(3) * rr * uy * uy) * R(1.0 / 3.0);
+    R zz = R(0), xz = R(0), yz = R(0);
+    if constexpr (D == 3) {
+      zz = (a[0][0][NK - 1] - R(3) * rr * uz * uz) * R(1.0 / 3.0);
+      xz = a[1][0][1] - rr * ux * uz;
+      yz = a[0][1][1] - rr * uy * uz;
+    }
+    om = smagorinsky_omega(xx, yy, zz, xy, xz, yz, rho, p);
+  }
+  const R omb = p.om_b;
   const R fs = R(1) - R(0.5) * om, fb = R(1) - R(0.5) * omb;
   // gamma in place
   // order 0 and 1: conserved (rate 0); the source gives sigma = 3 F_a
@@ -361,7 +416,7 @@ __host__ __device__ constexpr MrtBasis<L::Q> make_mrt_basis() {
   return B;
 }
 
-template <class L, class R>
+template <class L, class R, bool SMAG = false>
 __device__ __forceinline__ void collide_mrt_gs(R* f, const R* F, const CollideParams<R>& p) {
   constexpr MrtBasis<L::Q> B = make_mrt_basis<L>();
   R drho, jx, jy, jz;
@@ -382,6 +437,24 @@ __device__ __forceinline__ void collide_mrt_gs(R* f, const R* F, const CollidePa
     neq[q] = f[q] - w * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));
     src[q] = w * (R(3) * cF - uF3 + R(9) * cu * cF);
   }
+  R om = p.om;
+  if constexpr (SMAG) {
+    R xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+      if (cx != 0) xx += neq[q];
+      if (cy != 0) yy += neq[q];
+      if (cz != 0) zz += neq[q];
+      if (cx * cy == 1) xy += neq[q];
+      if (cx * cy == -1) xy -= neq[q];
+      if (cx * cz == 1) xz += neq[q];
+      if (cx * cz == -1) xz -= neq[q];
+      if (cy * cz == 1) yz += neq[q];
+      if (cy * cz == -1) yz -= neq[q];
+    }
+    om = smagorinsky_omega(xx, yy, zz, xy, xz, yz, rho, p);
+  }
   R gam[L::Q];
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
@@ -398,7 +471,7 @@ __device__ __forceinline__ void collide_mrt_gs(R* f, const R* F, const CollidePa
       for (int q = 0; q < L::Q; ++q)
         if (B.m[k][q] != 0.0) b += R(B.m[k][q]) * src[q];
     }
-    const R rate = grp == 0 ? R(0) : (grp == 1 ? p.om : (grp == 2 ? p.om_b : p.hi[grp - 3]));
+    const R rate = grp == 0 ? R(0) : (grp == 1 ? om : (grp == 2 ? p.om_b : p.hi[grp - 3]));
     gam[k] = (-rate * a + (R(1) - R(0.5) * rate) * b) * R(B.inv_norm[k]);
   }
 #pragma unroll
@@ -561,9 +634,12 @@ __device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const Col
 template <class L, int M, class R>
 __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>& p) {
   if constexpr (M == M_SRT) collide_srt<L>(f, F, p);
+  else if constexpr (M == M_SRT_SMAG) collide_srt<L, R, true>(f, F, p);
   else if constexpr (M == M_TRT) collide_trt<L>(f, F, p);
   else if constexpr (M == M_MRT && L::Q == 19) collide_mrt_gs<L>(f, F, p);
   else if constexpr (M == M_MRT) collide_mrt<L>(f, F, p);
+  else if constexpr (M == M_MRT_SMAG && L::Q == 19) collide_mrt_gs<L, R, true>(f, F, p);
+  else if constexpr (M == M_MRT_SMAG) collide_mrt<L, R, true>(f, F, p);
   else collide_cumulant<L>(f, F, p);
 }
 

@@ -22,6 +22,7 @@ struct Params {
   double rho0;
   double om, om_b, om_o;
   double hi[4];
+  double smag18;   // 18 C_S^2 (Smagorinsky), 0 = off
   int compressible;
 };
 

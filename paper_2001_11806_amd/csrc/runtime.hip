@@ -42,6 +42,7 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 struct lbm_ctx {
   lbm_config cfg{};
   int Q = 0;
+  int kmethod = 0;  // kernel method code: the ABI method, or its Smagorinsky variant
   Geo g{};
   Params p{};
   hipStream_t stream = nullptr;
@@ -117,6 +118,11 @@ int32_t validate(const lbm_config* cfg) {
     for (int i = 0; i < nhi; ++i)
       if (!rate_ok(r.omega_hi[i])) return fail(LBM_EINVAL, "omega_hi[%d] = %g is outside (0, 2)", i, r.omega_hi[i]);
   }
+  if (!(std::isfinite(r.cs_smag) && r.cs_smag >= 0)) return fail(LBM_EINVAL, "cs_smag must be >= 0");
+  if (r.cs_smag > 0 && cfg->method != LBM_SRT && cfg->method != LBM_MRT)
+    return fail(LBM_EUNSUPPORTED, "the Smagorinsky model is implemented for SRT and MRT");
+  if (r.cs_smag > 0 && cfg->checkpoint_every > 0)
+    return fail(LBM_EUNSUPPORTED, "the adjoint of the Smagorinsky model is not implemented");
   if (cfg->pattern != 0 && cfg->pattern != 1) return fail(LBM_EINVAL, "pattern must be 0 (two arrays) or 1 (AA)");
   if (!sweep_supported(cfg->stencil, cfg->method))
     return fail(LBM_EUNSUPPORTED, "method %d is not implemented on stencil %d", cfg->method, cfg->stencil);
@@ -158,6 +164,7 @@ Params make_params(const lbm_config& c) {
   p.om_o = c.rates.omega_odd > 0 ? c.rates.omega_odd
                                   : 1.0 / (c.rates.magic / (1.0 / c.rates.omega - 0.5) + 0.5);
   for (int i = 0; i < 4; ++i) p.hi[i] = c.rates.omega_hi[i];
+  p.smag18 = 18.0 * c.rates.cs_smag * c.rates.cs_smag;
   p.compressible = c.compressible;
   return p;
 }
@@ -179,7 +186,7 @@ int32_t alloc(void** p, size_t bytes, const char* what) {
 }
 
 int32_t sweep_once(lbm_ctx* c, const void* src, void* dst) {
-  HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, -1, src, dst, c->flags, c->force, c->g, c->p,
+  HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, src, dst, c->flags, c->force, c->g, c->p,
                        c->has_mask, c->stream),
           "sweep launch");
   return LBM_OK;
@@ -194,7 +201,7 @@ int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
 // One forward step on the context's stream.
 int32_t step_once(lbm_ctx* c) {
   if (is_aa(c)) {
-    HIP_TRY(launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
+    HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
                          c->force, c->g, c->p, c->has_mask, c->stream),
             "AA sweep launch");
   } else {
@@ -221,10 +228,10 @@ int32_t ensure_graph(lbm_ctx* c, int parity) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) {
     if (is_aa(c))   // parity = time parity: even / odd kernels alternate on one array
-      e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, cur, c->grid[0], nullptr, c->flags, c->force,
+      e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, cur, c->grid[0], nullptr, c->flags, c->force,
                        c->g, c->p, c->has_mask, c->cap_stream);
     else            // parity = current grid
-      e = launch_sweep(c->cfg.stencil, c->cfg.method, c->cfg.dtype, -1, c->grid[cur], c->grid[cur ^ 1], c->flags,
+      e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, c->grid[cur], c->grid[cur ^ 1], c->flags,
                        c->force, c->g, c->p, c->has_mask, c->cap_stream);
     cur ^= 1;
   }
@@ -281,6 +288,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   lbm_ctx* c = new lbm_ctx();
   c->cfg = *cfg;
   c->Q = q_of(cfg->stencil);
+  c->kmethod = cfg->rates.cs_smag > 0 ? (cfg->method == LBM_SRT ? 4 : 5) : cfg->method;
   c->g = make_geo(*cfg);
   c->p = make_params(*cfg);
   c->stream = (hipStream_t)hip_stream;

@@ -38,6 +38,7 @@ inline CollideParams<R> to_collide_params(const Params& p) {
   c.om_b = R(p.om_b);
   c.om_o = R(p.om_o);
   for (int i = 0; i < 4; ++i) c.hi[i] = R(p.hi[i]);
+  c.smag18 = R(p.smag18);
   c.compressible = p.compressible;
   return c;
 }

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_
 class Rates(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("omega_bulk", ctypes.c_double),
                 ("omega_odd", ctypes.c_double), ("magic", ctypes.c_double),
-                ("omega_hi", ctypes.c_double * 4)]
+                ("omega_hi", ctypes.c_double * 4), ("cs_smag", ctypes.c_double)]
 
 
 class Config(ctypes.Structure):
@@ -99,7 +99,7 @@ def _check(status):
 
 def make_config(stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0.0, magic=0.0,
                 omega_hi=(1.0, 1.0, 1.0, 1.0), rho0=1.0, compressible=True, pattern=0,
-                checkpoint_every=0, max_tape_steps=0, launch_mode=0):
+                checkpoint_every=0, max_tape_steps=0, launch_mode=0, cs_smag=0.0):
     nx, ny, nz = dims
     cfg = Config()
     cfg.stencil = STENCILS[stencil]
@@ -112,6 +112,7 @@ def make_config(stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0
     cfg.rates.magic = float(magic)
     for i in range(4):
         cfg.rates.omega_hi[i] = float(omega_hi[i])
+    cfg.rates.cs_smag = float(cs_smag)
     cfg.rho0 = float(rho0)
     cfg.compressible = 1 if compressible else 0
     cfg.pattern = int(pattern)
@@ -136,7 +137,7 @@ class LBM:
     def __init__(self, stencil, method, dtype, dims, omega, omega_bulk=1.0, omega_odd=0.0, magic=0.0,
                  omega_hi=(1.0, 1.0, 1.0, 1.0), rho0=1.0, compressible=True, mask=None,
                  checkpoint_every=0, max_tape_steps=0, device="cuda:0", stream=None, pattern=0,
-                 launch_mode=0):
+                 launch_mode=0, cs_smag=0.0):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -146,7 +147,8 @@ class LBM:
         self.Q = QS[stencil]
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
         self.cfg = make_config(stencil, method, dtype, dims, omega, omega_bulk, omega_odd, magic, omega_hi,
-                               rho0, compressible, pattern, checkpoint_every, max_tape_steps, launch_mode)
+                               rho0, compressible, pattern, checkpoint_every, max_tape_steps, launch_mode,
+                               cs_smag)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

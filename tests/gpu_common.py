@@ -40,6 +40,7 @@ def seeded_fields(stencil, dims, seed, amp=2e-2, with_mask=True):
 
 
 def make_gpu(stencil, method, dtype, dims, mask, rates=RATES, **kw):
+    kw.setdefault("cs_smag", rates.get("cs_smag", 0.0))
     return LBM(stencil, method, dtype, dims, rates["omega"], rates["omega_bulk"], rates["omega_odd"],
                rates["magic"], rates["omega_hi"], mask=mask, **kw)
 

@@ -238,3 +238,31 @@ def test_aa_set_get_pdfs_roundtrip_and_steps_from_it():
     want = orun.run(cfg, P, 7, mask, orun.force_field(F, dims))
     assert np.max(np.abs(to_np(g.get_pdfs()) - want)) <= 1e-13
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stencil,method", [("D2Q9", "SRT"), ("D2Q9", "MRT"), ("D3Q19", "SRT"), ("D3Q19", "MRT"),
+                                            ("D3Q27", "SRT"), ("D3Q27", "MRT")])
+def test_smagorinsky_parity(stencil, method, dtype):
+    """Smagorinsky model (local SRT rate / MRT shear rate) vs the oracle,
+    with walls and a body force; both patterns."""
+    need_gpu()
+    dims, mask, rho, u, F = _setup(stencil, method, dtype)
+    rates = dict(_rates(method), cs_smag=0.2)
+    cfg = oracle_cfg(stencil, method, "f64", rates)
+    Ff = orun.force_field(F, dims)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), STEPS, mask, Ff)
+    ro, uo = orun.readout(cfg, P, mask, Ff)
+    for pattern in (0, 1):
+        g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern, cs_smag=0.2)
+        g.set_force(F)
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+        g.step(STEPS)
+        _, ug = (to_np(t) for t in g.macroscopic())
+        Pg = to_np(g.get_pdfs())
+        g.close()
+        err = rel_l2(ug, uo)
+        print("smagorinsky", stencil, method, dtype, pattern, "rel L2 u %.2e" % err)
+        assert err <= BOUND_U[dtype]
+        if dtype == "f64":
+            assert np.max(np.abs(Pg - P)) <= 1e-13

@@ -264,3 +264,42 @@ def test_trt_magic_parameter():
     wo = collision.trt_odd_rate(r)
     assert abs((1 / r["omega"] - 0.5) * (1 / wo - 0.5) - 3.0 / 16.0) < 1e-15
     assert abs(1 / wo - 1.125) < 1e-14
+
+
+# -------------------------------------------------------------- Smagorinsky
+@pytest.mark.parametrize("name", STENCILS)
+def test_smagorinsky_rate_solves_paper_equations(name):
+    """The local rate satisfies the paper's Eq. (14) with |S| from Eq. (12)
+    (both written out here separately) for random non-equilibrium states."""
+    lat = lattice.velocity_set(name)
+    rng = np.random.default_rng(12)
+    f = _random_pdfs(lat, 50, rng, scale=0.05)
+    rho, u = eqm.macroscopic(lat, f)
+    feq = eqm.equilibrium(lat, rho, u)
+    cs, om0 = 0.17, 1.0 / 0.52
+    om = collision.smagorinsky_rate(lat, f, feq, rho, om0, cs)
+    c = lat.c.astype(float)
+    Pi = np.einsum("qa,qb,qn->abn", c, c, f - feq)
+    S = -3.0 * om / (2.0 * rho) * Pi                      # Eq. (12)
+    Snorm = np.sqrt(2.0 * (S * S).sum(axis=(0, 1)))
+    nu0 = (1.0 / om0 - 0.5) / 3.0
+    np.testing.assert_allclose(om, 2.0 / (6.0 * cs * cs * Snorm + 6.0 * nu0 + 1.0), rtol=1e-13)   # Eq. (14)
+    assert np.all(om < om0) and np.all(om > 0)
+
+
+@pytest.mark.parametrize("name,method", [("D2Q9", "SRT"), ("D3Q19", "SRT"), ("D3Q19", "MRT"), ("D3Q27", "MRT")])
+def test_smagorinsky_zero_constant_and_conservation(name, method):
+    lat = lattice.velocity_set(name)
+    rng = np.random.default_rng(13)
+    f = _random_pdfs(lat, 9, rng, scale=0.05)
+    F = 1e-4 * rng.standard_normal((3, 9))
+    if lat.d == 2:
+        F[2] = 0
+    base = collision.collide(method, lat, f, RATES, F)
+    np.testing.assert_array_equal(collision.collide(method, lat, f, dict(RATES, cs_smag=0.0), F), base)
+    out = collision.collide(method, lat, f, dict(RATES, cs_smag=0.2), F)
+    r0, j0 = eqm.density_momentum(lat, f)
+    r1, j1 = eqm.density_momentum(lat, out)
+    np.testing.assert_allclose(r1, r0, rtol=1e-14)
+    np.testing.assert_allclose(j1, j0 + F, atol=1e-15)
+    assert np.max(np.abs(out - base)) > 1e-6      # the model changes the result
