@@ -109,9 +109,10 @@ typedef struct {
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when
  * checkpoint_every > 0) and copies the solid mask in.
- * solid_mask_host: N bytes on the host, 1 = solid, 0 = fluid, or NULL (all
- *   fluid, fully periodic).  Solid cells are never updated and read out as
- *   rho = u = 0.
+ * solid_mask_host: N bytes on the host: 0 = fluid, 1 = resting wall,
+ *   2..127 = moving-wall types (see lbm_set_wall_velocity), or NULL (all fluid,
+ *   fully periodic); larger values are LBM_EINVAL.  Solid cells are never
+ *   updated and read out as rho = u = 0.
  * hip_stream: a hipStream_t of the current device, or NULL.
  * On success *out owns all allocations; release with lbm_destroy.
  * The PDFs are initialised to rest at rho0 (shifted zero). */
@@ -125,6 +126,15 @@ int32_t lbm_destroy(lbm_ctx* ctx);
  * F == NULL and profile_y = ny*3 host doubles, force (Fx, Fy, Fz) of row y at
  * [3*y + a] (uniform in x and z).  Invalidates a recorded tape. */
 int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
+
+/* Velocity of the moving-wall type `wall_type` (2..127): solid cells whose mask
+ * value is wall_type act as a wall moving with u (3 host doubles).  A
+ * population re-entering along link q from such a wall is the cell's own
+ * outgoing opposite population plus 2 w_q rho0 (c_q . u) / c_s^2 (velocity
+ * bounce-back, Sec. III-C "Boundary Conditions").  Mask value 1 is the resting
+ * wall; all types start at rest.  With pattern 1 call it before
+ * lbm_init_equilibrium / lbm_set_pdfs.  Invalidates a recorded tape. */
+int32_t lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u);
 
 /* P = f^eq(rho, u) (Eq. 3) at fluid cells; resets the step counter and tape.
  * rho_dev: N values or NULL (rho0 everywhere); u_dev: 3*N values or NULL

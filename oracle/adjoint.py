@@ -67,7 +67,7 @@ def collision_jacobian(lat, g, omega, F):
     return J, B
 
 
-def trajectory(cfg, rho_init, u_init, solid, F, T):
+def trajectory(cfg, rho_init, u_init, solid, F, T, wall_velocity=None):
     """Forward states P^0 .. P^T (float64, no storage rounding)."""
     lat = cfg.lat
     s = solid.astype(bool)
@@ -77,7 +77,7 @@ def trajectory(cfg, rho_init, u_init, solid, F, T):
     Ff = np.broadcast_to(np.asarray(F, float).reshape(3, 1, 1, 1), (3,) + s.shape)
     from .collision import srt
     for _ in range(T):
-        g = stream_pull(lat, P, s)
+        g = stream_pull(lat, P, solid, wall_velocity, cfg.rho0)
         post = srt(lat, g, cfg.rates, Ff)
         P = np.where(s[None], P, post)
         Ps.append(P)
@@ -120,12 +120,14 @@ def seed(cfg, P, solid, F, dL_du, dL_drho=None):
     return lam, dF
 
 
-def adjoint_step(cfg, P_t, lam_next, solid, F):
-    """lambda^t from lambda^{t+1}, plus this step's dL/dF contribution."""
+def adjoint_step(cfg, P_t, lam_next, solid, F, wall_velocity=None):
+    """lambda^t from lambda^{t+1}, plus this step's dL/dF contribution.  The
+    moving-wall term of the gather is a constant: it shifts the state at which
+    the Jacobian is taken but adds nothing to the transpose."""
     lat = cfg.lat
     s = solid.astype(bool)
     fl = ~s
-    g = stream_pull(lat, P_t, s)
+    g = stream_pull(lat, P_t, solid, wall_velocity, cfg.rho0)
     shp = g.shape[1:]
     J, B = collision_jacobian(lat, g.reshape(lat.Q, -1), cfg.rates["omega"], F)
     lam2 = lam_next.reshape(lat.Q, -1)
@@ -161,19 +163,19 @@ def init_gradient(cfg, rho_init, u_init, lam0, solid):
     return du, drho
 
 
-def gradient(cfg, rho_init, u_init, solid, F, T, loss=outlet_loss):
+def gradient(cfg, rho_init, u_init, solid, F, T, loss=outlet_loss, wall_velocity=None):
     """Full reverse sweep: returns (L, dL/du_init, dL/drho_init, dL/dF)."""
-    Ps = trajectory(cfg, rho_init, u_init, solid, F, T)
+    Ps = trajectory(cfg, rho_init, u_init, solid, F, T, wall_velocity)
     L, dL_du = loss(cfg, Ps[T], solid, F)
     lam, dF = seed(cfg, Ps[T], solid, F, dL_du)
     for t in range(T - 1, -1, -1):
-        lam, dFt = adjoint_step(cfg, Ps[t], lam, solid, F)
+        lam, dFt = adjoint_step(cfg, Ps[t], lam, solid, F, wall_velocity)
         dF = dF + dFt
     du, drho = init_gradient(cfg, rho_init, u_init, lam, solid)
     return L, du, drho, dF
 
 
-def tangent(cfg, rho_init, u_init, solid, F, T, du0, dF, loss=outlet_loss):
+def tangent(cfg, rho_init, u_init, solid, F, T, du0, dF, loss=outlet_loss, wall_velocity=None):
     """Forward-mode derivative of the loss along (du0, dF)."""
     lat = cfg.lat
     s = solid.astype(bool)
@@ -187,10 +189,10 @@ def tangent(cfg, rho_init, u_init, solid, F, T, du0, dF, loss=outlet_loss):
                                + cu * c[:, a].reshape(-1, 1, 1, 1) / CS2 ** 2 - u_init[a] / CS2)
         dP += dfeq * du0[a]
     dP = np.where(fl[None], dP, 0.0)
-    Ps = trajectory(cfg, rho_init, u_init, solid, F, T)
+    Ps = trajectory(cfg, rho_init, u_init, solid, F, T, wall_velocity)
     dFv = np.asarray(dF, float)
     for t in range(T):
-        g = stream_pull(lat, Ps[t], s)
+        g = stream_pull(lat, Ps[t], solid, wall_velocity, cfg.rho0)
         dg = stream_pull(lat, dP, s)
         J, B = collision_jacobian(lat, g.reshape(lat.Q, -1), cfg.rates["omega"], F)
         new = np.einsum("qpn,pn->qn", J, dg.reshape(lat.Q, -1)) + np.einsum("qbn,b->qn", B, dFv)

@@ -96,12 +96,13 @@ def init_equilibrium(cfg, rho, u, solid=None):
     return quantize(cfg, P)
 
 
-def step(cfg, P, solid=None, force=None):
+def step(cfg, P, solid=None, force=None, wall_velocity=None):
     """One stream-pull-collide step (two-array pattern).
 
-    ``force``: None or an array (3, nz, ny, nx) from ``force_field``.
+    ``force``: None or an array (3, nz, ny, nx) from ``force_field``;
+    ``wall_velocity``: None or a table (K, 3) indexed by the mask value.
     """
-    g = stream_pull(cfg.lat, P, solid)
+    g = stream_pull(cfg.lat, P, solid, wall_velocity, cfg.rho0)
     post = collide(cfg.method, cfg.lat, g, cfg.rates, force, cfg.rho0, cfg.compressible)
     post = quantize(cfg, post)
     if solid is not None:
@@ -109,9 +110,9 @@ def step(cfg, P, solid=None, force=None):
     return post
 
 
-def run(cfg, P, nsteps, solid=None, force=None):
+def run(cfg, P, nsteps, solid=None, force=None, wall_velocity=None):
     for _ in range(nsteps):
-        P = step(cfg, P, solid, force)
+        P = step(cfg, P, solid, force, wall_velocity)
     return P
 
 
@@ -138,13 +139,13 @@ def conserved(cfg, P, solid=None):
     return np.array([rho.sum(), j[0].sum(), j[1].sum(), j[2].sum()])
 
 
-def step_at_cells(cfg, P_of, cells, dims, solid=None, force=None):
+def step_at_cells(cfg, P_of, cells, dims, solid=None, force=None, wall_velocity=None):
     """One step evaluated only at ``cells`` (linear indices, x fastest).
 
     ``P_of(q, idx)`` gives the stored state at linear cell indices.
     ``force`` is None, (3,) or a per-y profile (ny, 3).  Returns (Q, ncells).
     """
-    g = gather_at(cfg.lat, P_of, cells, dims, solid)
+    g = gather_at(cfg.lat, P_of, cells, dims, solid, wall_velocity, cfg.rho0)
     F = None
     if force is not None:
         F = np.asarray(force, dtype=np.float64)

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
   if (c.valid && !(fl & 1)) {
     R f[L::Q];
     uint32_t bb = 0;
-    gather<L, T>(P, flags, fl, c, g, f, &bb);
+    gather<L, T>(P, flags, fl, c, g, f, &bb, p.wall, p.rho0);
     R lam[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];

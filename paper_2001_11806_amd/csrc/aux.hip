@@ -95,9 +95,12 @@ __device__ __forceinline__ void block_sum(double (&v)[W]) {
 //   2  AA, after an odd kernel or after initialisation: slot (x + c_q, q),
 //      or (x, opp q) when x + c_q is solid.
 // Solid cells keep their own slots (x, q) in every layout.
+//   In layout 2 a bounced slot holds the re-entering population, i.e. the
+//   outgoing one plus the moving-wall term, which is removed / added here.
 template <class L, class T>
 __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int has_mask, int layout,
-                                          const CellIdx& c, const Geo& g, double* v) {
+                                          const CellIdx& c, const Geo& g, double* v,
+                                          const typename Storage<T>::R* wall, double rho0) {
   const size_t N = (size_t)g.N;
   const bool solid = has_mask && (flags[c.cell] & 1);
   if (layout == 0 || solid) {
@@ -111,15 +114,17 @@ __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int 
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const bool bb = q > 0 && has_mask && (flags[d] & 1);
-      v[q] = (double)Storage<T>::load(bb ? P + opp<L>(q) * N + c.cell : P + q * N + d);
+      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      v[q] = (double)Storage<T>::load((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d);
+      if (fs & 1) v[q] -= (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0);
     }
   }
 }
 
 template <class L, class T>
 __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_mask, int layout, const CellIdx& c,
-                                           const Geo& g, const double* v) {
+                                           const Geo& g, const double* v, const typename Storage<T>::R* wall,
+                                           double rho0) {
   const size_t N = (size_t)g.N;
   const bool solid = has_mask && (flags[c.cell] & 1);
   if (layout == 0 || solid) {
@@ -133,21 +138,27 @@ __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_m
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const bool bb = q > 0 && has_mask && (flags[d] & 1);
-      store_from_double(bb ? P + opp<L>(q) * N + c.cell : P + q * N + d, v[q]);
+      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      if (fs & 1)
+        store_from_double(P + opp<L>(q) * N + c.cell,
+                          v[q] + (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0));
+      else
+        store_from_double(P + q * N + d, v[q]);
     }
   }
 }
 
 // --------------------------------------------------------------- flags
-// bit 0: solid; bit 1: fluid cell with at least one solid upstream neighbour.
+// bit 0: solid (bits 1..7 then hold the wall type); for fluid cells bit 1:
+// at least one solid upstream neighbour.
 template <class L>
 __global__ __launch_bounds__(512) void k_build_flags(const uint8_t* __restrict__ solid, uint8_t* __restrict__ flags,
                                                      Geo g) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   LBM_NEIGHBOURS(c, g)
-  uint8_t f = solid[c.cell] ? 1 : 0;
+  // solid cells: bit 0 set, bits 1..7 = wall type (the mask value)
+  uint8_t f = solid[c.cell] ? (uint8_t)(1u | ((unsigned)solid[c.cell] << 1)) : 0;
   if (!f) {
     bool near = false;
 #pragma unroll
@@ -169,7 +180,7 @@ hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags,
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_init(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
                                               const void* rho, const void* u, int fdt, Geo g, double rho0,
-                                              int compressible) {
+                                              int compressible, const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(512) void k_init(T* P, const uint8_t* __restrict__ 
       v[q] = weight<L>(q) * ((r - rho0) + rr * (3.0 * cu + 4.5 * cu * cu - usq));
     }
   }
-  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
 }
 
 hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
@@ -200,7 +211,8 @@ hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, in
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_init<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags, has_mask,
-                         layout, rho, u, field_dtype, g, p.rho0, p.compressible);
+                         layout, rho, u, field_dtype, g, p.rho0, p.compressible,
+                         (const typename Storage<T>::R*)p.wall);
       return hipGetLastError();
     })
   })
@@ -212,14 +224,14 @@ template <class L, class T>
 __global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                  int has_mask, int layout, const typename Storage<T>::R* __restrict__ force_y,
                                                  void* rho_out, void* u_out, int fdt, Geo g, double rho0,
-                                                 int compressible) {
+                                                 int compressible, const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double r = 0, ux = 0, uy = 0, uz = 0;
   if (!(has_mask && (flags[c.cell] & 1))) {
     double f[L::Q];
-    load_post<L, T>(P, flags, has_mask, layout, c, g, f);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, f, wall, rho0);
     double d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -250,7 +262,8 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
     LBM_DTYPE_SWITCH(dtype, {
       using R = typename Storage<T>::R;
       hipLaunchKernelGGL((k_readout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, layout, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible);
+                         has_mask, layout, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible,
+                         (const R*)p.wall);
       return hipGetLastError();
     })
   })
@@ -260,13 +273,13 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_conserved(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                    int has_mask, int layout, double* __restrict__ partials, Geo g,
-                                                   double rho0) {
+                                                   double rho0, const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   const size_t N = (size_t)g.N;
   double v[4] = {0, 0, 0, 0};
   if (c.valid && !(has_mask && (flags[c.cell] & 1))) {
     double pf[L::Q];
-    load_post<L, T>(P, flags, has_mask, layout, c, g, pf);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, pf, wall, rho0);
     double d = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -308,7 +321,7 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
     using L = decltype(lat);
     using T = decltype(tag);
     hipLaunchKernelGGL((k_conserved<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, layout, partials, g, p.rho0);
+                       has_mask, layout, partials, g, p.rho0, (const typename Storage<T>::R*)p.wall);
     return hipGetLastError();
   };
   auto by_dtype = [&](auto lat) -> hipError_t {
@@ -334,26 +347,27 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                   int has_mask, int layout, double* __restrict__ out, Geo g,
-                                                  double rho0) {
+                                                  double rho0, const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double v[L::Q];
-  load_post<L, T>(P, flags, has_mask, layout, c, g, v);
+  load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) out[q * N + c.cell] = v[q] + weight<L>(q) * rho0;
 }
 
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_set_pdfs(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
-                                                  const double* __restrict__ in, Geo g, double rho0) {
+                                                  const double* __restrict__ in, Geo g, double rho0,
+                                                  const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double v[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) v[q] = in[q * N + c.cell] - weight<L>(q) * rho0;
-  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
 }
 
 hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
@@ -361,7 +375,7 @@ hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t*
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, layout, out, g, p.rho0);
+                         has_mask, layout, out, g, p.rho0, (const typename Storage<T>::R*)p.wall);
       return hipGetLastError();
     })
   })
@@ -372,7 +386,7 @@ hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags,
-                         has_mask, layout, in, g, p.rho0);
+                         has_mask, layout, in, g, p.rho0, (const typename Storage<T>::R*)p.wall);
       return hipGetLastError();
     })
   })

@@ -27,7 +27,9 @@ struct CollideParams {
   R hi[4];    // orders 3..6
   R smag18;   // 18 C_S^2
   int compressible;
+  const R* wall;  // wall velocity table [128][3]
 };
+
 
 // Smagorinsky model (Sec. III-C "Turbulence models", Eqs. 11-14): eddy
 // viscosity (C_S Delta)^2 |S| with Delta = 1 and the strain rate from the
@@ -57,6 +59,16 @@ __device__ __forceinline__ R cdot(int q, R x, R y, R z) {
   if (L::c(q, 2) == 1) s += z;
   if (L::c(q, 2) == -1) s -= z;
   return s;
+}
+
+// Velocity bounce-back term (Sec. III-C "Boundary Conditions"): the missing
+// population of link q is the cell's own outgoing opposite population plus
+// 2 w_q rho_0 (c_q . u_w) / c_s^2, u_w the velocity of wall type k (row k of
+// the table; row 1, the resting wall, is zero).
+template <class L, class R>
+__device__ __forceinline__ R wall_term(int q, int k, const R* wall, R rho0) {
+  const R* u = wall + 3 * k;
+  return R(6.0 * weight<L>(q)) * rho0 * cdot<L>(q, u[0], u[1], u[2]);
 }
 
 template <class L, class R>

@@ -24,6 +24,7 @@ struct Params {
   double hi[4];
   double smag18;   // 18 C_S^2 (Smagorinsky), 0 = off
   int compressible;
+  const void* wall; // device table [128][3] of wall velocities (compute type), row = wall id
 };
 
 inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }

@@ -52,6 +52,7 @@ struct lbm_ctx {
   uint8_t* flags = nullptr;
   int has_mask = 0;
   void* force = nullptr;       // compute type, 3 * ny
+  void* wall = nullptr;        // compute type, [128][3] wall velocities by wall type
   double* partials = nullptr;  // 4 doubles per block
   double* acc = nullptr;       // [0..2] adjoint dL/dF, [4..7] conservation totals
   double* adj_acc = nullptr;   // 3 doubles per block: dL/dF accumulated over adjoint steps
@@ -82,7 +83,7 @@ void free_ctx(lbm_ctx* c) {
   for (auto& ge : c->graph_exec)
     if (ge) (void)hipGraphExecDestroy(ge);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->partials, c->acc, c->adj_acc, c->tape,
+  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->wall, c->partials, c->acc, c->adj_acc, c->tape,
                   c->seg,     c->init_fields, c->lam[0], c->lam[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -285,6 +286,12 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   *out = nullptr;
   int32_t st = validate(cfg);
   if (st != LBM_OK) return st;
+  if (solid_mask_host) {
+    const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
+    for (size_t i = 0; i < n; ++i)
+      if (solid_mask_host[i] > 127)
+        return fail(LBM_EINVAL, "mask value %d at cell %zu: wall types are 1..127", solid_mask_host[i], i);
+  }
   lbm_ctx* c = new lbm_ctx();
   c->cfg = *cfg;
   c->Q = q_of(cfg->stencil);
@@ -303,6 +310,8 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   for (int i = 0; i < (cfg->pattern == 1 ? 1 : 2); ++i)
     if ((st = alloc(&c->grid[i], c->grid_bytes, "PDF grid")) != LBM_OK) return bail(st);
   if ((st = alloc(&c->force, 3 * (size_t)cfg->ny * rb, "force table")) != LBM_OK) return bail(st);
+  if ((st = alloc(&c->wall, 3 * 128 * rb, "wall velocity table")) != LBM_OK) return bail(st);
+  c->p.wall = c->wall;
   if ((st = alloc((void**)&c->partials, (size_t)nblk * 4 * sizeof(double), "reduction partials")) != LBM_OK)
     return bail(st);
   if ((st = alloc((void**)&c->acc, 8 * sizeof(double), "accumulators")) != LBM_OK) return bail(st);
@@ -321,6 +330,8 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   hipError_t e;
   if ((e = launch_fill_zero(c->force, 3 * (size_t)cfg->ny * rb, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "force table init"));
+  if ((e = launch_fill_zero(c->wall, 3 * 128 * rb, c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "wall table init"));
   if ((e = launch_fill_zero(c->acc, 8 * sizeof(double), c->stream)) != hipSuccess)
     return bail(hip_fail(e, "accumulator init"));
   if (solid_mask_host) {
@@ -386,6 +397,27 @@ int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y) {
   }
   if (e != hipSuccess) return hip_fail(e, "force upload");
   ctx->tape_ok = false;  // a recorded trajectory no longer matches the force
+  ctx->adj_t = -1;
+  return LBM_OK;
+}
+
+int32_t lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u) {
+  if (!ctx || !u) return fail(LBM_EINVAL, "NULL argument");
+  if (wall_type < 2 || wall_type > 127) return fail(LBM_EINVAL, "wall_type must be in 2..127 (1 is the resting wall)");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(u[a])) return fail(LBM_EINVAL, "wall velocity component %d is not finite", a);
+  if (ctx->cfg.stencil == LBM_D2Q9 && u[2] != 0.0) return fail(LBM_EINVAL, "D2Q9 wall velocity must have u_z = 0");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_wall_velocity sync");
+  const size_t off = 3 * (size_t)wall_type;
+  if (ctx->cfg.dtype == LBM_F64) {
+    e = hipMemcpy((double*)ctx->wall + off, u, 3 * sizeof(double), hipMemcpyHostToDevice);
+  } else {
+    const float uf[3] = {(float)u[0], (float)u[1], (float)u[2]};
+    e = hipMemcpy((float*)ctx->wall + off, uf, 3 * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "wall velocity upload");
+  ctx->tape_ok = false;  // a recorded trajectory no longer matches the walls
   ctx->adj_t = -1;
   return LBM_OK;
 }

@@ -40,6 +40,7 @@ inline CollideParams<R> to_collide_params(const Params& p) {
   for (int i = 0; i < 4; ++i) c.hi[i] = R(p.hi[i]);
   c.smag18 = R(p.smag18);
   c.compressible = p.compressible;
+  c.wall = (const R*)p.wall;
   return c;
 }
 
@@ -111,7 +112,8 @@ __device__ __forceinline__ const T* row_base(const T* src, int q, int y, int z, 
 // own outgoing population opp(q).  Bit q of *bb is set for bounced links.
 template <class L, class T>
 __device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t* __restrict__ flags, int fl,
-                                       const CellIdx& c, const Geo& g, typename Storage<T>::R* f, uint32_t* bb) {
+                                       const CellIdx& c, const Geo& g, typename Storage<T>::R* f, uint32_t* bb,
+                                       const typename Storage<T>::R* wall, typename Storage<T>::R rho0) {
   LBM_NEIGHBOURS(c, g)
   const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(T), (uint32_t)c.x * (uint32_t)sizeof(T),
                           (uint32_t)xm * (uint32_t)sizeof(T)};  // source x for c_x = -1, 0, +1
@@ -126,8 +128,9 @@ __device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t*
       const int sx = cx > 0 ? xm : (cx < 0 ? xp : c.x);
       const int sy = cy > 0 ? ym : (cy < 0 ? yp : c.y);
       const int sz = cz > 0 ? zm : (cz < 0 ? zp : c.z);
-      if (flags[(sz * g.ny + sy) * g.nx + sx] & 1) {
-        f[q] = Storage<T>::load(src + (size_t)opp<L>(q) * (size_t)g.N + c.cell);
+      const int fs = flags[(sz * g.ny + sy) * g.nx + sx];
+      if (fs & 1) {   // solid: bits 1..7 hold the wall type
+        f[q] = Storage<T>::load(src + (size_t)opp<L>(q) * (size_t)g.N + c.cell) + wall_term<L>(q, fs >> 1, wall, rho0);
         m |= 1u << q;
       }
     }
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
     if (fl & 1) return;  // solid cells are never updated
   }
   R f[L::Q];
-  gather<L, T>(src, flags, fl, c, g, f, nullptr);
+  gather<L, T>(src, flags, fl, c, g, f, nullptr, p.wall, p.rho0);
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
   store_cell<T, NT>(dst, c, g, f, L::Q);
@@ -242,9 +245,10 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
     f[q] = Storage<T>::load(at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]));
   if (fl & 2) {
 #pragma unroll
-    for (int q = 1; q < L::Q; ++q)
-      if (flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] & 1)
-        f[q] = Storage<T>::load(A + (size_t)q * (size_t)g.N + c.cell);
+    for (int q = 1; q < L::Q; ++q) {
+      const int fs = flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)];
+      if (fs & 1) f[q] = Storage<T>::load(A + (size_t)q * (size_t)g.N + c.cell) + wall_term<L>(q, fs >> 1, p.wall, p.rho0);
+    }
   }
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
@@ -257,8 +261,9 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
     // opposite slot; solid cells' slots are never written
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      if (q > 0 && (flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] & 1))
-        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, f[q]);
+      const int fs = q > 0 ? flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] : 0;
+      if (fs & 1)   // the population that re-enters along opp(q) carries the wall term
+        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, f[q] + wall_term<L>(opp<L>(q), fs >> 1, p.wall, p.rho0));
       else
         put<T, NT>(at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]),
                    f[q]);

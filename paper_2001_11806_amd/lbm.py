@@ -49,6 +49,7 @@ SIGNATURES = {
     "lbm_create": ([ctypes.POINTER(Config), _P, _P, ctypes.POINTER(_P)], _I32),
     "lbm_destroy": ([_P], _I32),
     "lbm_set_force": ([_P, _DP, _DP], _I32),
+    "lbm_set_wall_velocity": ([_P, _I32, _DP], _I32),
     "lbm_init_equilibrium": ([_P, _P, _P, _I32], _I32),
     "lbm_step": ([_P, _I32], _I32),
     "lbm_get_macroscopic": ([_P, _P, _P, _I32], _I32),
@@ -207,6 +208,10 @@ class LBM:
             _check(self.lib.lbm_set_force(self.h, None, prof.ctypes.data_as(_DP)))
         else:
             _check(self.lib.lbm_set_force(self.h, None, None))
+
+    def set_wall_velocity(self, wall_type, u):
+        arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(u, dtype=np.float64).reshape(3)])
+        _check(self.lib.lbm_set_wall_velocity(self.h, int(wall_type), arr))
 
     def init_equilibrium(self, rho=None, u=None):
         r, dr = self._field(rho, 1, "rho")

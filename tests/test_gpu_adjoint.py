@@ -111,3 +111,31 @@ def test_adjoint_state_errors():
     with pytest.raises(LBMError, match="t = 0"):
         g.adjoint_grads()
     g.close()
+
+
+def test_adjoint_with_moving_wall_matches_oracle():
+    need_gpu()
+    dims = (70, 10, 6)
+    mask, rho, u0, F, T = _case("D3Q19", dims)
+    mask = mask.copy()
+    mask[:, -1, :] = 2
+    u0 = u0 * (mask == 0)
+    table = np.zeros((3, 3))
+    table[2] = (0.03, 0.0, 0.01)
+    g = make_gpu("D3Q19", "SRT", "f64", dims, mask, RATES, checkpoint_every=4, max_tape_steps=T)
+    g.set_force(F)
+    g.set_wall_velocity(2, table[2])
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+    g.step(T)
+    _, u_T = g.macroscopic()
+    dL = torch.zeros_like(u_T)
+    fl = torch.tensor(mask == 0, device=u_T.device)
+    dL[0, :, :, -1] = 2 * u_T[0, :, :, -1] * fl[:, :, -1]
+    g.adjoint_seed(dL)
+    g.adjoint_step(T)
+    du, _, dF = g.adjoint_grads()
+    g.close()
+    cfg = orun.Config("D3Q19", "SRT", RATES)
+    L, gu, grho, gF = oadj.gradient(cfg, rho, u0, mask, F, T, wall_velocity=table)
+    assert rel_l2(to_np(du), gu) <= 1e-10
+    np.testing.assert_allclose(dF, gF, rtol=1e-10)

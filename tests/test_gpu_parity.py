@@ -266,3 +266,65 @@ def test_smagorinsky_parity(stencil, method, dtype):
         assert err <= BOUND_U[dtype]
         if dtype == "f64":
             assert np.max(np.abs(Pg - P)) <= 1e-13
+
+
+WALL_TABLE = np.zeros((4, 3))
+WALL_TABLE[2] = (0.02, 0.0, 0.0)
+WALL_TABLE[3] = (0.0, -0.01, 0.015)
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stencil,method", [("D2Q9", "TRT"), ("D3Q19", "SRT"), ("D3Q19", "MRT"), ("D3Q27", "TRT"),
+                                            ("D3Q27", "MRT")])
+def test_moving_walls_parity(stencil, method, dtype, pattern):
+    """Velocity bounce-back with several wall types (mask values 1, 2, 3)
+    vs the oracle, both patterns."""
+    need_gpu()
+    dims, mask, rho, u, F = _setup(stencil, method, dtype)
+    mask = mask.copy()
+    mask[:, -1, :] = 2
+    rng = np.random.default_rng(21)
+    mask[(mask == 1) & (rng.random(mask.shape) < 0.3)] = 3
+    u = u * (mask == 0)
+    table = WALL_TABLE.copy()
+    if stencil == "D2Q9":
+        table[:, 2] = 0
+    rates = _rates(method)
+    g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern)
+    g.set_force(F)
+    for k in (2, 3):
+        g.set_wall_velocity(k, table[k])
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(STEPS + 1)
+    _, ug = (to_np(t) for t in g.macroscopic())
+    Pg = to_np(g.get_pdfs())
+    g.close()
+    cfg = oracle_cfg(stencil, method, "f64", rates)
+    Ff = orun.force_field(F, dims)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), STEPS + 1, mask, Ff, table)
+    _, uo = orun.readout(cfg, P, mask, Ff)
+    err = rel_l2(ug, uo)
+    print("moving walls", stencil, method, dtype, pattern, "rel L2 u %.2e" % err)
+    assert err <= BOUND_U[dtype]
+    if dtype == "f64":
+        assert np.max(np.abs(Pg - P)) <= 1e-13
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+def test_couette_exact_on_gpu(pattern):
+    """Moving top wall over a resting wall: exact linear profile (FP64)."""
+    need_gpu()
+    H, U = 12, 0.01
+    ny = H + 2
+    mask = np.zeros((1, ny, 1), dtype=np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, ny - 1, :] = 2
+    g = make_gpu("D3Q19", "TRT", "f64", (1, ny, 1), mask, RATES, pattern=pattern)
+    g.set_wall_velocity(2, (U, 0, 0))
+    g.init_equilibrium()
+    g.step(6000)
+    _, uu = g.macroscopic()
+    g.close()
+    y = np.arange(1, H + 1)
+    np.testing.assert_allclose(to_np(uu)[0, 0, 1:H + 1, 0], U * (y - 0.5) / H, rtol=1e-9, atol=1e-14)
