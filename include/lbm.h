@@ -103,8 +103,9 @@ typedef struct {
 
 /* Supported combinations: SRT, TRT, MRT on all stencils (MRT rates: orders
  * 3..6 on D3Q27, orders 3 and 4 on D2Q9 and D3Q19);
- * CUMULANT on D2Q9 and D3Q27 with omega_hi all equal to 1, compressible and
- * without body force; both patterns for every method; the adjoint tape for
+ * CUMULANT on D2Q9 and D3Q27, compressible and without body force (higher-order
+ * rates all 1 use a Gaussian-reconstruction kernel, other rates a general FP64
+ * cumulant kernel); both patterns for every method; the adjoint tape for
  * compressible SRT with pattern 0.  Others return LBM_EUNSUPPORTED. */
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when

@@ -16,7 +16,7 @@ namespace lbm {
 
 // Internal method codes: the ABI's four, plus SRT and MRT with the
 // Smagorinsky model (local shear rate).
-enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5 };
+enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5, M_CUMULANT_GEN = 6 };
 
 template <class R>
 struct CollideParams {
@@ -643,6 +643,196 @@ __device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const Col
       }
 }
 
+// ---------------------------------------------------------------- cumulant, general rates
+// Cumulant collision (Eq. 9, Sec. III-B) with arbitrary rates for orders 3..6.
+// populations -> central moments c (per-axis 3-point transforms about u)
+// -> cumulants: with the first central moments zero, kappa_S is the sum over
+// set partitions of S into blocks of size >= 2 of
+// (-1)^(k-1) (k-1)! prod c_B (k blocks); orders 2 and 3 equal the central
+// moments.  Relaxation as in the unit-rate kernel, kappa*_n = (1 - omega_n)
+// kappa_n for n >= 3; the inverse relation (all coefficients +1) rebuilds the
+// central moments and the back-transform the populations.  Computed in FP64
+// for every storage type: the order 4-6 relations subtract products of
+// O(c_s^4) terms.
+template <class L, class R>
+__device__ __forceinline__ void collide_cumulant_general(R* f, const R* /*F*/, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
+  constexpr double cs2 = 1.0 / 3.0;
+  const double rho0 = (double)p.rho0;
+  double c[3][3][NK];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
+        c[i][j][k] = (double)f[q] + weight<L>(q) * rho0;
+      }
+  double rho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const double v = c[i][j][k];
+        rho += v;
+        jx += (i - 1) * v;
+        jy += (j - 1) * v;
+        if constexpr (D == 3) jz += (k - 1) * v;
+      }
+  const double inv = 1.0 / rho;
+  const double u[3] = {jx * inv, jy * inv, jz * inv};
+  // forward transforms: (f-, f0, f+) -> central moments about v
+  auto fwd = [](double& a, double& b, double& e, double v) {
+    const double m0 = a + b + e, m1 = e - a, m2 = e + a;
+    a = m0;
+    b = m1 - v * m0;
+    e = m2 - 2.0 * v * m1 + v * v * m0;
+  };
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) fwd(c[0][j][k], c[1][j][k], c[2][j][k], u[0]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) fwd(c[i][0][k], c[i][1][k], c[i][2][k], u[1]);
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) fwd(c[i][j][0], c[i][j][1], c[i][j][2], u[2]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) c[i][j][k] *= inv;
+  const double om = (double)p.om, omb = (double)p.om_b;
+  const double h3 = 1.0 - (double)p.hi[0], h4 = 1.0 - (double)p.hi[1];
+  const double h5 = 1.0 - (double)p.hi[2], h6 = 1.0 - (double)p.hi[3];
+  if constexpr (D == 2) {
+    const double c20 = c[2][0][0], c02 = c[0][2][0], c11 = c[1][1][0];
+    const double k22 = c[2][2][0] - c20 * c02 - 2.0 * c11 * c11;
+    // second order: shear (traceless + off-diagonal) and bulk (trace)
+    const double tr = 0.5 * (c20 + c02 - 2.0 * cs2);
+    const double K20 = cs2 + (1.0 - om) * (c20 - cs2 - tr) + (1.0 - omb) * tr;
+    const double K02 = cs2 + (1.0 - om) * (c02 - cs2 - tr) + (1.0 - omb) * tr;
+    const double K11 = (1.0 - om) * c11;
+    c[2][0][0] = K20;
+    c[0][2][0] = K02;
+    c[1][1][0] = K11;
+    c[2][1][0] *= h3;
+    c[1][2][0] *= h3;
+    c[2][2][0] = h4 * k22 + K20 * K02 + 2.0 * K11 * K11;
+  } else {
+    // second-order central moments = cumulants
+    const double x2 = c[2][0][0], y2 = c[0][2][0], z2 = c[0][0][2];
+    const double xy = c[1][1][0], xz = c[1][0][1], yz = c[0][1][1];
+    // third order (= central moments)
+    const double x2y = c[2][1][0], x2z = c[2][0][1], xy2 = c[1][2][0], y2z = c[0][2][1], xz2 = c[1][0][2],
+                 yz2 = c[0][1][2], xyz = c[1][1][1];
+    // fourth order cumulants
+    const double k220 = c[2][2][0] - x2 * y2 - 2.0 * xy * xy;
+    const double k202 = c[2][0][2] - x2 * z2 - 2.0 * xz * xz;
+    const double k022 = c[0][2][2] - y2 * z2 - 2.0 * yz * yz;
+    const double k211 = c[2][1][1] - x2 * yz - 2.0 * xy * xz;
+    const double k121 = c[1][2][1] - y2 * xz - 2.0 * xy * yz;
+    const double k112 = c[1][1][2] - z2 * xy - 2.0 * xz * yz;
+    // fifth order
+    const double k221 = c[2][2][1] - x2 * y2z - y2 * x2z - 4.0 * xy * xyz - 2.0 * xz * xy2 - 2.0 * yz * x2y;
+    const double k212 = c[2][1][2] - x2 * yz2 - z2 * x2y - 4.0 * xz * xyz - 2.0 * xy * xz2 - 2.0 * yz * x2z;
+    const double k122 = c[1][2][2] - y2 * xz2 - z2 * xy2 - 4.0 * yz * xyz - 2.0 * xy * yz2 - 2.0 * xz * y2z;
+    // sixth order
+    const double k222 = c[2][2][2] -
+                        (x2 * c[0][2][2] + y2 * c[2][0][2] + z2 * c[2][2][0] + 4.0 * xy * c[1][1][2] +
+                         4.0 * xz * c[1][2][1] + 4.0 * yz * c[2][1][1]) -
+                        (2.0 * x2y * yz2 + 2.0 * x2z * y2z + 2.0 * xy2 * xz2 + 4.0 * xyz * xyz) +
+                        2.0 * (x2 * y2 * z2 + 2.0 * x2 * yz * yz + 2.0 * y2 * xz * xz + 2.0 * z2 * xy * xy +
+                               8.0 * xy * xz * yz);
+    // relax
+    const double tr = (x2 + y2 + z2 - 3.0 * cs2) / 3.0;
+    const double X2 = cs2 + (1.0 - om) * (x2 - cs2 - tr) + (1.0 - omb) * tr;
+    const double Y2 = cs2 + (1.0 - om) * (y2 - cs2 - tr) + (1.0 - omb) * tr;
+    const double Z2 = cs2 + (1.0 - om) * (z2 - cs2 - tr) + (1.0 - omb) * tr;
+    const double XY = (1.0 - om) * xy, XZ = (1.0 - om) * xz, YZ = (1.0 - om) * yz;
+    const double X2Y = h3 * x2y, X2Z = h3 * x2z, XY2 = h3 * xy2, Y2Z = h3 * y2z, XZ2 = h3 * xz2, YZ2 = h3 * yz2,
+                 XYZ = h3 * xyz;
+    const double K220 = h4 * k220, K202 = h4 * k202, K022 = h4 * k022, K211 = h4 * k211, K121 = h4 * k121,
+                 K112 = h4 * k112;
+    const double K221 = h5 * k221, K212 = h5 * k212, K122 = h5 * k122, K222 = h6 * k222;
+    // back to central moments
+    c[2][0][0] = X2;
+    c[0][2][0] = Y2;
+    c[0][0][2] = Z2;
+    c[1][1][0] = XY;
+    c[1][0][1] = XZ;
+    c[0][1][1] = YZ;
+    c[2][1][0] = X2Y;
+    c[2][0][1] = X2Z;
+    c[1][2][0] = XY2;
+    c[0][2][1] = Y2Z;
+    c[1][0][2] = XZ2;
+    c[0][1][2] = YZ2;
+    c[1][1][1] = XYZ;
+    const double C220 = K220 + X2 * Y2 + 2.0 * XY * XY;
+    const double C202 = K202 + X2 * Z2 + 2.0 * XZ * XZ;
+    const double C022 = K022 + Y2 * Z2 + 2.0 * YZ * YZ;
+    const double C211 = K211 + X2 * YZ + 2.0 * XY * XZ;
+    const double C121 = K121 + Y2 * XZ + 2.0 * XY * YZ;
+    const double C112 = K112 + Z2 * XY + 2.0 * XZ * YZ;
+    c[2][2][0] = C220;
+    c[2][0][2] = C202;
+    c[0][2][2] = C022;
+    c[2][1][1] = C211;
+    c[1][2][1] = C121;
+    c[1][1][2] = C112;
+    c[2][2][1] = K221 + X2 * Y2Z + Y2 * X2Z + 4.0 * XY * XYZ + 2.0 * XZ * XY2 + 2.0 * YZ * X2Y;
+    c[2][1][2] = K212 + X2 * YZ2 + Z2 * X2Y + 4.0 * XZ * XYZ + 2.0 * XY * XZ2 + 2.0 * YZ * X2Z;
+    c[1][2][2] = K122 + Y2 * XZ2 + Z2 * XY2 + 4.0 * YZ * XYZ + 2.0 * XY * YZ2 + 2.0 * XZ * Y2Z;
+    // sixth order: partitions {6}, {2,4}, {3,3}, {2,2,2}, expressed with the
+    // relaxed cumulants of orders 2..4
+    c[2][2][2] = K222 +
+                 (X2 * K022 + Y2 * K202 + Z2 * K220 + 4.0 * XY * K112 + 4.0 * XZ * K121 + 4.0 * YZ * K211) +
+                 (2.0 * X2Y * YZ2 + 2.0 * X2Z * Y2Z + 2.0 * XY2 * XZ2 + 4.0 * XYZ * XYZ) +
+                 (X2 * Y2 * Z2 + 2.0 * X2 * YZ * YZ + 2.0 * Y2 * XZ * XZ + 2.0 * Z2 * XY * XY + 8.0 * XY * XZ * YZ);
+  }
+  // back-transforms with the mean velocity, then scale by rho
+  auto bwd = [](double& a, double& b, double& e, double v) {
+    const double k0 = a, k1 = b, k2 = e, v2 = v * v;
+    a = 0.5 * (k0 * (v2 - v) + k1 * (2.0 * v - 1.0) + k2);
+    b = k0 * (1.0 - v2) - 2.0 * v * k1 - k2;
+    e = 0.5 * (k0 * (v2 + v) + k1 * (2.0 * v + 1.0) + k2);
+  };
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) bwd(c[i][j][0], c[i][j][1], c[i][j][2], u[2]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) bwd(c[i][0][k], c[i][1][k], c[i][2][k], u[1]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) bwd(c[0][j][k], c[1][j][k], c[2][j][k], u[0]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
+        f[q] = R(rho * c[i][j][k] - weight<L>(q) * rho0);
+      }
+}
+
 template <class L, int M, class R>
 __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>& p) {
   if constexpr (M == M_SRT) collide_srt<L>(f, F, p);
@@ -652,6 +842,7 @@ __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>
   else if constexpr (M == M_MRT) collide_mrt<L>(f, F, p);
   else if constexpr (M == M_MRT_SMAG && L::Q == 19) collide_mrt_gs<L, R, true>(f, F, p);
   else if constexpr (M == M_MRT_SMAG) collide_mrt<L, R, true>(f, F, p);
+  else if constexpr (M == M_CUMULANT_GEN) collide_cumulant_general<L>(f, F, p);
   else collide_cumulant<L>(f, F, p);
 }
 

@@ -127,13 +127,8 @@ int32_t validate(const lbm_config* cfg) {
   if (cfg->pattern != 0 && cfg->pattern != 1) return fail(LBM_EINVAL, "pattern must be 0 (two arrays) or 1 (AA)");
   if (!sweep_supported(cfg->stencil, cfg->method))
     return fail(LBM_EUNSUPPORTED, "method %d is not implemented on stencil %d", cfg->method, cfg->stencil);
-  if (cfg->method == LBM_CUMULANT) {
-    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
-    for (int i = 0; i < nhi; ++i)
-      if (r.omega_hi[i] != 1.0)
-        return fail(LBM_EUNSUPPORTED, "the cumulant sweep implements higher-order rates equal to 1 only");
-    if (!cfg->compressible) return fail(LBM_EUNSUPPORTED, "the cumulant operator is compressible only");
-  }
+  if (cfg->method == LBM_CUMULANT && !cfg->compressible)
+    return fail(LBM_EUNSUPPORTED, "the cumulant operator is compressible only");
   if (cfg->launch_mode != 0 && cfg->launch_mode != 1) return fail(LBM_EINVAL, "launch_mode must be 0 or 1");
   if (cfg->checkpoint_every < 0) return fail(LBM_EINVAL, "checkpoint_every must be >= 0");
   if (cfg->checkpoint_every > 0) {
@@ -296,6 +291,11 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   c->cfg = *cfg;
   c->Q = q_of(cfg->stencil);
   c->kmethod = cfg->rates.cs_smag > 0 ? (cfg->method == LBM_SRT ? 4 : 5) : cfg->method;
+  if (cfg->method == LBM_CUMULANT) {   // unit higher-order rates: the Gaussian-reconstruction kernel
+    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
+    for (int i = 0; i < nhi; ++i)
+      if (cfg->rates.omega_hi[i] != 1.0) c->kmethod = 6;
+  }
   c->g = make_geo(*cfg);
   c->p = make_params(*cfg);
   c->stream = (hipStream_t)hip_stream;

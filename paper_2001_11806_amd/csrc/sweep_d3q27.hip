@@ -7,6 +7,8 @@ namespace lbm {
 hipError_t launch_sweep_d3q27(int method, int dtype, int phase, const void* src, void* dst, const uint8_t* flags,
                           const void* force_y, const Geo& g, const Params& p, int has_mask, hipStream_t s) {
   switch (method) {
+    case M_CUMULANT_GEN:
+      return sweep_for_dtype<D3Q27, M_CUMULANT_GEN>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
     case M_SRT_SMAG:
       return sweep_for_dtype<D3Q27, M_SRT_SMAG>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
     case M_MRT_SMAG:

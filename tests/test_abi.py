@@ -75,7 +75,7 @@ def _create(lib, **kw):
     (dict(method="MRT", stencil="D3Q27", omega_hi=(1, 1, 2.0, 1)), B.EINVAL, "omega_hi"),
     (dict(method="MRT", omega_hi=(1, 2.5, 1, 1)), B.EINVAL, "omega_hi[1]"),
     (dict(method="CUMULANT"), B.EUNSUPPORTED, "not implemented"),
-    (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 1.2, 1, 1)), B.EUNSUPPORTED, "equal to 1"),
+    (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 2.2, 1, 1)), B.EINVAL, "omega_hi[1]"),
     (dict(method="CUMULANT", stencil="D3Q27", compressible=False), B.EUNSUPPORTED, "compressible"),
     (dict(pattern=2), B.EINVAL, "pattern"),
     (dict(pattern=1, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "two-array pattern"),
