@@ -80,10 +80,10 @@ class Timer:
 
 
 def run_forward(torch, LBM, inputs, stencil, method, dtype, dims, rates, mask, u, F=None, profile=None,
-                steps=100, warmup=10, pattern=0):
+                steps=100, warmup=10, pattern=0, cs_smag=0.0):
     lbm = LBM(stencil, method, dtype, dims, rates["omega"], rates.get("omega_bulk", 1.0),
               rates.get("omega_odd", 0.0), rates.get("magic", 0.0), rates.get("omega_hi", (1.0,) * 4),
-              mask=mask, pattern=pattern)
+              mask=mask, pattern=pattern, cs_smag=cs_smag)
     if F is not None:
         lbm.set_force(F)
     if profile is not None:
@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,aa,copy,c1,c3,c4,c5)")
+    ap.add_argument("--only", default="", help="comma list of extras to run (fp32,aa,copy,methods,c1,c3,c4,c5)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU halo exchange is not built "
@@ -208,6 +208,9 @@ def main():
         del ref, u3
         torch.cuda.empty_cache()
 
+    if want("methods"):
+        extras["method_comparison"] = bench_methods(torch, LBM, inputs, Timer, run_forward)
+
     if want("c1"):
         extras["c1_d2q9_srt_64_f64"] = bench_c1(torch, LBM, inputs, Timer)
 
@@ -270,6 +273,37 @@ def main():
     print(json.dumps(result))
 
 
+def bench_methods(torch, LBM, inputs, Timer, run_forward):
+    """Per-method throughput on the same lattice (the paper compares TRT,
+    Smagorinsky, weighted MRT and cumulant kernels with the AA pattern and
+    finds them all memory bound): D3Q19 256^3 channel FP64 with AA, and
+    D3Q27 256^3 periodic FP32 two-array."""
+    out = {}
+    n = 256
+    mask, _, u = inputs.channel_flow(n, seed=2, amp=1e-3)
+    F = np.array([1e-6, 0.0, 0.0])
+    base = dict(omega=1 / 0.8, omega_bulk=1.2, magic=3 / 16, omega_odd=0.0, omega_hi=(1.0,) * 4)
+    for name, method, extra in (("SRT", "SRT", {}), ("TRT", "TRT", {}), ("MRT", "MRT", {}),
+                                ("SRT_Smagorinsky", "SRT", {"cs_smag": 0.1}),
+                                ("MRT_Smagorinsky", "MRT", {"cs_smag": 0.1})):
+        r = run_forward(torch, LBM, inputs, "D3Q19", method, "f64", (n, n, n), dict(base, **extra), mask, u, F=F,
+                        steps=50, warmup=5, pattern=1, cs_smag=extra.get("cs_smag", 0.0))
+        r.pop("u_out")
+        out["D3Q19_f64_AA_" + name] = {"mlups": r["mlups"], "GBps": r["achieved_GBps"]}
+        log("  D3Q19 f64 AA %-16s %7.0f MLUPS %6.0f GB/s" % (name, r["mlups"], r["achieved_GBps"]))
+    u27 = inputs.uniform_noise_velocity((n, n, n), 1e-3, 6, None, dtype=np.float32)
+    for name, method, rates in (("SRT", "SRT", base), ("TRT", "TRT", base), ("MRT", "MRT", base),
+                                ("CUMULANT", "CUMULANT", dict(base, omega_bulk=1.0)),
+                                ("CUMULANT_general_rates", "CUMULANT", dict(base, omega_bulk=1.0,
+                                                                            omega_hi=(1.2, 1.1, 1.0, 1.3)))):
+        r = run_forward(torch, LBM, inputs, "D3Q27", method, "f32", (n, n, n), rates, None, u27, steps=50, warmup=5)
+        r.pop("u_out")
+        out["D3Q27_f32_" + name] = {"mlups": r["mlups"], "GBps": r["achieved_GBps"]}
+        log("  D3Q27 f32    %-22s %7.0f MLUPS %6.0f GB/s" % (name, r["mlups"], r["achieved_GBps"]))
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_c1(torch, LBM, inputs, Timer):
     """C1: D2Q9 SRT 64^2 Taylor-Green, FP64, 1000 steps; launch-latency bound,
     so the graph replay (launch_mode 0) is timed beside direct launches."""
@@ -323,7 +357,8 @@ def bench_adjoint(torch, LBM, inputs, Timer):
 
 def cpu_baseline(inputs):
     """The oracle as it stands, one host thread, on a bounded sample of the
-    headline workload: a 256 x 64 x 32 slice of the channel, 10 steps."""
+    headline workload: a 256 x 64 x 32 slice of the channel, stepped until
+    at least 10 s of work (at most 60 steps)."""
     from threadpoolctl import threadpool_limits
     from oracle import run as orun
     dims = (256, 64, 32)
@@ -334,11 +369,13 @@ def cpu_baseline(inputs):
     with threadpool_limits(1):
         P = orun.init_equilibrium(cfg, np.ones((32, 64, 256)), u, mask)
         t0 = time.time()
-        steps = 10
-        P = orun.run(cfg, P, steps, mask, Ff)
+        steps = 0
+        while steps < 60 and (steps < 2 or time.time() - t0 < 10.0):
+            P = orun.step(cfg, P, mask, Ff)
+            steps += 1
         dt = time.time() - t0
     cells = dims[0] * dims[1] * dims[2]
-    log("CPU oracle: %.2f MLUPS (%.1f s)" % (cells * steps / dt / 1e6, dt))
+    log("CPU oracle: %.2f MLUPS (%d steps, %.1f s)" % (cells * steps / dt / 1e6, steps, dt))
     return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": "numpy FP64 oracle, D3Q19 TRT channel 256x64x32 (same recipe as the headline), "
                       "%d steps, %.1f s, one host thread" % (steps, dt)}
