@@ -216,6 +216,9 @@ def main():
 
     if want("c4"):
         extras["c4_d3q19_srt_adjoint_128_f32"] = bench_adjoint(torch, LBM, inputs, Timer)
+        aa = bench_adjoint(torch, LBM, inputs, Timer, pattern=1)
+        aa["gradients_equal_to_two_array"] = aa["dL_dF"] == extras["c4_d3q19_srt_adjoint_128_f32"]["dL_dF"]
+        extras["c4_d3q19_srt_adjoint_128_f32_aa"] = aa
         torch.cuda.empty_cache()
 
     if want("c5"):
@@ -323,14 +326,16 @@ def bench_c1(torch, LBM, inputs, Timer):
     return out
 
 
-def bench_adjoint(torch, LBM, inputs, Timer):
+def bench_adjoint(torch, LBM, inputs, Timer, pattern=0):
     """C4: D3Q19 SRT 128^3 channel with 5% spheres, FP32, 200 steps forward,
-    tape every 20, adjoint back to t=0 (segment recompute included)."""
+    tape every 20, adjoint back to t=0 (segment recompute included); pattern 1
+    runs the forward sweep and the adjoint in one array each (AA)."""
     n, T, k = 128, 200, 20
-    log("C4 D3Q19 SRT adjoint 128^3 f32, T=%d, k=%d" % (T, k))
+    log("C4 D3Q19 SRT adjoint 128^3 f32, T=%d, k=%d, %s" % (T, k, "AA" if pattern else "two arrays"))
     mask = inputs.sphere_channel_mask(n, seed=4)
     u0 = inputs.uniform_noise_velocity((n, n, n), 1e-3, 4, mask, dtype=np.float32)
-    lbm = LBM("D3Q19", "SRT", "f32", (n, n, n), 1 / 0.8, mask=mask, checkpoint_every=k, max_tape_steps=T)
+    lbm = LBM("D3Q19", "SRT", "f32", (n, n, n), 1 / 0.8, mask=mask, checkpoint_every=k, max_tape_steps=T,
+              pattern=pattern)
     lbm.set_force([1e-5, 0, 0])
     u0t = torch.from_numpy(u0).cuda()
     fl = torch.from_numpy(mask == 0).cuda()
@@ -350,6 +355,7 @@ def bench_adjoint(torch, LBM, inputs, Timer):
     fluid = cells - int(mask.sum())
     per_step = fluid * (2 * 19 * 4) * 2 + fluid * 3 * 19 * 4 + 3 * cells   # fwd + recompute + adjoint
     sec = (tf.ms + tb.ms) / 1e3
+    log("  %.0f MLUPS effective (forward %.1f ms, backward %.1f ms)" % (cells * T / sec / 1e6, tf.ms, tb.ms))
     return {"fwd_adjoint_mlups": cells * T / sec / 1e6, "forward_ms": tf.ms, "backward_ms": tb.ms,
             "algorithmic_GBps": per_step * T / sec / 1e9, "dL_dF": [float(v) for v in dF],
             "dL_du0_norm": float(du.double().norm())}

@@ -93,7 +93,8 @@ typedef struct {
   int32_t compressible;     /* 1: rho_0 = rho in Eq. (3) (default); 0: incompressible */
   int32_t pattern;          /* 0: two arrays, stream-pull-collide (Sec. IV-B);
                                1: AA pattern in one array (Sec. IV-B, Fig. "AA update
-                               pattern"): half the memory, no adjoint tape          */
+                               pattern"): half the memory; with a tape the adjoint
+                               state is one array as well                           */
   int32_t checkpoint_every; /* k > 0 enables the adjoint tape (PDF copy every k steps) */
   int32_t max_tape_steps;   /* longest forward run the tape covers (adjoint only)   */
   int32_t launch_mode;      /* 0: automatic -- lattices of at most 64 MiB per grid without a
@@ -106,7 +107,7 @@ typedef struct {
  * CUMULANT on D2Q9 and D3Q27, compressible and without body force (higher-order
  * rates all 1 use a Gaussian-reconstruction kernel, other rates a general FP64
  * cumulant kernel); both patterns for every method; the adjoint tape for
- * compressible SRT with pattern 0.  Others return LBM_EUNSUPPORTED. */
+ * compressible SRT with either pattern.  Others return LBM_EUNSUPPORTED. */
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when
  * checkpoint_every > 0) and copies the solid mask in.
@@ -168,11 +169,14 @@ int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
 /* Number of steps taken since the last init / set_pdfs. */
 int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t);
 
-/* ---- discrete adjoint (SRT, compressible, two-array pattern) ----------
+/* ---- discrete adjoint (SRT, compressible) ------------------------------
  * Forward map: P^0 = f^eq(rho_init, u_init) from lbm_init_equilibrium,
  * P^{t+1} = collide(pull-gather(P^t)), readout as lbm_get_macroscopic.
  * The adjoint state lambda^t = dL/dP^t runs backwards through the transposed
- * collision Jacobian and the transposed gather (reverse streaming).
+ * collision Jacobian and the transposed gather (reverse streaming).  With
+ * pattern 1 the tape stores each checkpoint in the two-array layout and
+ * lambda lives in one array, updated in place by the transposes of the AA
+ * kernels; the gradients equal those of pattern 0.
  *
  * Seed lambda^T from dL/drho and dL/du at the current step T (fields of type
  * field_dtype, dL_drho_dev may be NULL).  Needs checkpoint_every > 0 and

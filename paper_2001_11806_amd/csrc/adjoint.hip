@@ -18,6 +18,15 @@
 //   sum_q lambda_q dS_q/dF_b + beta_b / (2 rho)
 //   = (1 - omega/2) [sum_q c_qb lambda_q w_q (3 + 9 c.u) - 3 u_b s0] + beta_b / (2 rho),
 // reduced per block in FP64.
+//
+// AA pattern (one array, Sec. IV-B): lambda lives in one array too, placed
+// like the stored state of the same time.  Each forward AA kernel reads and
+// writes the same set of slots per cell, so its transpose does as well: the
+// adjoint of the even kernel reads lambda from the cell's own slots opp(q)
+// and writes h to its own slots q; the adjoint of the odd kernel reads
+// lambda from the slots the forward kernel pushed to, (x + c_q, q) or
+// (x, opp q) at a wall, and writes h to the slots it pulled from,
+// (x - c_q, opp q) or (x, q) at a wall.  Both run in place without races.
 #include "sweep.h"
 
 namespace lbm {
@@ -56,16 +65,35 @@ __device__ __forceinline__ void st_f(void* p, size_t i, double v, int fdt) {
     ((float*)p)[i] = (float)v;
 }
 
+// Linear index (plane * N + cell) of the slot that holds population q of the
+// fluid cell c in a stored layout (0 two arrays; 1 AA inverted; 2 AA
+// streamed, see load_post).
+template <class L>
+__device__ __forceinline__ size_t post_slot(int layout, int q, const CellIdx& c, const Geo& g,
+                                            const uint8_t* flags, int has_mask) {
+  const size_t N = (size_t)g.N;
+  if (layout == 0) return (size_t)q * N + c.cell;
+  if (layout == 1) return (size_t)opp<L>(q) * N + c.cell;
+  LBM_NEIGHBOURS(c, g)
+  const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
+  const bool bounced = q > 0 && has_mask && (flags[d] & 1);
+  return bounced ? (size_t)opp<L>(q) * N + c.cell : (size_t)q * N + d;
+}
+
 // ------------------------------------------------------------------ seed
 // lambda^T_q = dL/drho + sum_a dL/du_a (c_qa - u_a)/rho with the readout
 // rho = sum P, u = (sum c P - F/2)/rho; the readout also gives dL/dF its
 // direct term -sum_x dL/du(x) / (2 rho(x)).
+// The seed writes every slot: solid cells' own slots get 0, and the fluid
+// values land on the fluid slots one to one in every layout.
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                  int has_mask, const typename Storage<T>::R* __restrict__ force_y,
+                                                  int has_mask, int layout,
+                                                  const typename Storage<T>::R* __restrict__ force_y,
                                                   const void* dL_drho, const void* dL_du, int fdt,
                                                   typename Storage<T>::R* __restrict__ lam,
-                                                  double* __restrict__ partials, Geo g, double rho0) {
+                                                  double* __restrict__ partials, Geo g, double rho0,
+                                                  const typename Storage<T>::R* wall) {
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   const size_t N = (size_t)g.N;
@@ -77,8 +105,15 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
       for (int q = 0; q < L::Q; ++q) lam[q * N + c.cell] = R(0);
     } else {
       R f[L::Q];
+      if (layout == 0) {
 #pragma unroll
-      for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(P + q * N + c.cell);
+        for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(P + q * N + c.cell);
+      } else {
+        double v[L::Q];
+        load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) f[q] = R(v[q]);
+      }
       R drho, jx, jy, jz;
       density_momentum<L>(f, drho, jx, jy, jz);
       const R rho = R(rho0) + drho;
@@ -91,7 +126,8 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
       const R gr = dL_drho ? R(ld_f(dL_drho, c.cell, fdt)) : R(0);
       const R base = gr - (gx * ux + gy * uy + gz * uz) * inv;
 #pragma unroll
-      for (int q = 0; q < L::Q; ++q) lam[q * N + c.cell] = base + cdot<L>(q, gx, gy, gz) * inv;
+      for (int q = 0; q < L::Q; ++q)
+        lam[post_slot<L>(layout, q, c, g, flags, has_mask)] = base + cdot<L>(q, gx, gy, gz) * inv;
       dF[0] = -(double)gx / (2.0 * (double)rho);
       dF[1] = -(double)gy / (2.0 * (double)rho);
       dF[2] = -(double)gz / (2.0 * (double)rho);
@@ -103,9 +139,55 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
 }
 
 // ------------------------------------------------------------------ sweep
-// Each block adds its dL/dF contribution to its own FP64 accumulator slot
-// (only that block's thread 0 touches the slot, launches are stream-ordered),
-// so the sum is deterministic and needs no reduction launch per step.
+// One fluid cell: lam (lambda^{t+1} of the cell, Q values) becomes h = J^T lam
+// in place, for the pre-collision populations f; dF receives the cell's
+// dL/dF contribution.
+template <class L, class R>
+__device__ __forceinline__ void adj_cell(const R* f, R* lam, R F0, R F1, R F2, const CollideParams<R>& p,
+                                         double* dF) {
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  const R rho = p.rho0 + drho;
+  const R inv = R(1) / rho;
+  const R ux = (jx + R(0.5) * F0) * inv, uy = (jy + R(0.5) * F1) * inv, uz = (jz + R(0.5) * F2) * inv;
+  const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R om = p.om, fs = R(1) - R(0.5) * p.om;
+  const R omr3 = R(3) * om * rho;
+  R alpha = R(0), s0 = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R w = R(weight<L>(q));
+    const R cu = cdot<L>(q, ux, uy, uz);
+    const R cF = cdot<L>(q, F0, F1, F2);
+    const R lw = lam[q] * w;
+    alpha += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+    s0 += lw;
+    const R t = lw * (omr3 * (R(1) + R(3) * cu) + R(9) * fs * cF);
+    const R sf = lw * (R(3) + R(9) * cu);
+    if (L::c(q, 0) == 1) { bx += t; sx += sf; }
+    if (L::c(q, 0) == -1) { bx -= t; sx -= sf; }
+    if (L::c(q, 1) == 1) { by += t; sy += sf; }
+    if (L::c(q, 1) == -1) { by -= t; sy -= sf; }
+    if (L::c(q, 2) == 1) { bz += t; sz += sf; }
+    if (L::c(q, 2) == -1) { bz -= t; sz -= sf; }
+  }
+  alpha *= om;
+  bx -= R(3) * (om * rho * ux + fs * F0) * s0;
+  by -= R(3) * (om * rho * uy + fs * F1) * s0;
+  bz -= R(3) * (om * rho * uz + fs * F2) * s0;
+  const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
+  const R one_m = R(1) - om;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) lam[q] = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
+  dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
+  dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
+  dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
+}
+
+// Two lambda arrays.  Each block adds its dL/dF contribution to its own FP64
+// accumulator slot (only that block's thread 0 touches the slot, launches
+// are stream-ordered), so the sum is deterministic and needs no reduction
+// launch per step.
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                    int has_mask, const typename Storage<T>::R* __restrict__ force_y,
@@ -126,39 +208,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
     R lam[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];
-    const R F0 = force_y[3 * c.y], F1 = force_y[3 * c.y + 1], F2 = force_y[3 * c.y + 2];
-    R drho, jx, jy, jz;
-    density_momentum<L>(f, drho, jx, jy, jz);
-    const R rho = p.rho0 + drho;
-    const R inv = R(1) / rho;
-    const R ux = (jx + R(0.5) * F0) * inv, uy = (jy + R(0.5) * F1) * inv, uz = (jz + R(0.5) * F2) * inv;
-    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    const R om = p.om, fs = R(1) - R(0.5) * p.om;
-    const R omr3 = R(3) * om * rho;
-    R alpha = R(0), s0 = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-      const R w = R(weight<L>(q));
-      const R cu = cdot<L>(q, ux, uy, uz);
-      const R cF = cdot<L>(q, F0, F1, F2);
-      const R lw = lam[q] * w;
-      alpha += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
-      s0 += lw;
-      const R t = lw * (omr3 * (R(1) + R(3) * cu) + R(9) * fs * cF);
-      const R sf = lw * (R(3) + R(9) * cu);
-      if (L::c(q, 0) == 1) { bx += t; sx += sf; }
-      if (L::c(q, 0) == -1) { bx -= t; sx -= sf; }
-      if (L::c(q, 1) == 1) { by += t; sy += sf; }
-      if (L::c(q, 1) == -1) { by -= t; sy -= sf; }
-      if (L::c(q, 2) == 1) { bz += t; sz += sf; }
-      if (L::c(q, 2) == -1) { bz -= t; sz -= sf; }
-    }
-    alpha *= om;
-    bx -= R(3) * (om * rho * ux + fs * F0) * s0;
-    by -= R(3) * (om * rho * uy + fs * F1) * s0;
-    bz -= R(3) * (om * rho * uz + fs * F2) * s0;
-    const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
-    const R one_m = R(1) - om;
+    adj_cell<L, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
     // h goes back along the link it was pulled through: the upstream slot
     // (x - c_q, q), addressed like the gather; a bounced link's upstream slot
     // belongs to a solid cell (written at most once, never read) and its
@@ -168,7 +218,6 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
                             (uint32_t)xm * (uint32_t)sizeof(R)};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      lam[q] = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
       R* row = const_cast<R*>(row_base<L>((const R*)lam_out, q, c.y, c.z, ym, yp, zm, zp, g));
       *at_bytes(row, ox[L::c(q, 0) + 1]) = lam[q];
     }
@@ -177,9 +226,64 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
       for (int q = 1; q < L::Q; ++q)
         if ((bb >> q) & 1u) lam_out[(size_t)opp<L>(q) * N + c.cell] = lam[q];
     }
-    dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
-    dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
-    dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
+  }
+  block_sum_adj<3>(dF);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] += dF[k];
+}
+
+// One lambda array (AA pattern), in place; ODD selects the adjoint of the
+// odd kernel.  P is the forward state of the reversed step in the two-array
+// layout (the tape and the recomputed segment hold that layout).
+template <class L, class T, int ODD>
+__global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                      int has_mask,
+                                                      const typename Storage<T>::R* __restrict__ force_y,
+                                                      typename Storage<T>::R* A, double* __restrict__ partials,
+                                                      Geo g, CollideParams<typename Storage<T>::R> p) {
+  using R = typename Storage<T>::R;
+  const CellIdx c = cell_of(g);
+  const size_t N = (size_t)g.N;
+  double dF[3] = {0, 0, 0};
+  int fl = 0;
+  if (c.valid && has_mask) fl = flags[c.cell];
+  if (c.valid && !(fl & 1)) {
+    R f[L::Q];
+    uint32_t bb = 0;   // bit q: x - c_q is solid (so x + c_opp(q) is solid)
+    gather<L, T>(P, flags, fl, c, g, f, &bb, p.wall, p.rho0);
+    LBM_NEIGHBOURS(c, g)
+    const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(R), (uint32_t)c.x * (uint32_t)sizeof(R),
+                            (uint32_t)xm * (uint32_t)sizeof(R)};  // x - c_x for c_x = -1, 0, +1
+    R* own = A + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+    R lam[L::Q];
+    if (!ODD) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) lam[q] = *at_bytes(own + (size_t)opp<L>(q) * N, ox[1]);
+    } else {
+      // forward push slot of q: (x + c_q, q), or (x, opp q) when x + c_q is solid
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q)
+        lam[q] = *at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]);
+      if (bb) {
+#pragma unroll
+        for (int q = 1; q < L::Q; ++q)
+          if ((bb >> opp<L>(q)) & 1u) lam[q] = *at_bytes(own + (size_t)opp<L>(q) * N, ox[1]);
+      }
+    }
+    adj_cell<L, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
+    if (!ODD) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) *at_bytes(own + (size_t)q * N, ox[1]) = lam[q];
+    } else {
+      // forward pull slot of q: (x - c_q, opp q), or (x, q) when x - c_q is solid
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) {
+        if ((bb >> q) & 1u)
+          *at_bytes(own + (size_t)q * N, ox[1]) = lam[q];
+        else
+          *at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]) = lam[q];
+      }
+    }
   }
   block_sum_adj<3>(dF);
   if (threadIdx.x == 0)
@@ -191,7 +295,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
 //                      dL/drho = sum_q lambda_q w_q (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u).
 template <class L, class R>
 __global__ __launch_bounds__(512) void k_adj_init_grad(const R* __restrict__ lam, const uint8_t* __restrict__ flags,
-                                                       int has_mask, const R* __restrict__ init_fields,
+                                                       int has_mask, int layout, const R* __restrict__ init_fields,
                                                        void* dL_du0, void* dL_drho0, int fdt, Geo g) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
@@ -204,7 +308,7 @@ __global__ __launch_bounds__(512) void k_adj_init_grad(const R* __restrict__ lam
     R ax = 0, ay = 0, az = 0, s0 = 0, r = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      const R lw = lam[q * N + c.cell] * R(weight<L>(q));
+      const R lw = lam[post_slot<L>(layout, q, c, g, flags, has_mask)] * R(weight<L>(q));
       const R cu = cdot<L>(q, ux, uy, uz);
       r += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
       s0 += lw;
@@ -260,41 +364,51 @@ static hipError_t by_stencil_dtype(int stencil, int dtype, F&& fn) {
 }
 
 hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
-                               const void* force_y, const void* dL_drho, const void* dL_du, int field_dtype,
-                               void* lam, double* partials, const Geo& g, const Params& p, hipStream_t s) {
+                               int layout, const void* force_y, const void* dL_drho, const void* dL_du,
+                               int field_dtype, void* lam, double* partials, const Geo& g, const Params& p,
+                               hipStream_t s) {
   return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     using R = typename Storage<T>::R;
     hipLaunchKernelGGL((k_adj_seed<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam, partials, g, p.rho0);
+                       has_mask, layout, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam, partials, g,
+                       p.rho0, (const R*)p.wall);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_adjoint_sweep(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
-                                const void* force_y, const void* lam_in, void* lam_out, double* partials,
+hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
+                                int has_mask, const void* force_y, void* lam_in, void* lam_out, double* partials,
                                 const Geo& g, const Params& p, hipStream_t s) {
   return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     using R = typename Storage<T>::R;
     const CollideParams<R> cp = to_collide_params<R>(p);
-    hipLaunchKernelGGL((k_adj_sweep<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, (const R*)force_y, (const R*)lam_in, (R*)lam_out, partials, g, cp);
+    const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
+    if (phase < 0)
+      hipLaunchKernelGGL((k_adj_sweep<L, T>), grid, block, 0, s, (const T*)P, flags, has_mask, (const R*)force_y,
+                         (const R*)lam_in, (R*)lam_out, partials, g, cp);
+    else if (phase == 0)
+      hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 0>), grid, block, 0, s, (const T*)P, flags, has_mask,
+                         (const R*)force_y, (R*)lam_in, partials, g, cp);
+    else
+      hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 1>), grid, block, 0, s, (const T*)P, flags, has_mask,
+                         (const R*)force_y, (R*)lam_in, partials, g, cp);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags, int has_mask,
-                                    const void* init_fields, void* dL_du0, void* dL_drho0, int field_dtype,
-                                    const Geo& g, const Params& p, hipStream_t s) {
+                                    int layout, const void* init_fields, void* dL_du0, void* dL_drho0,
+                                    int field_dtype, const Geo& g, const Params& p, hipStream_t s) {
   (void)p;
   auto run = [&](auto lat, auto rtag) -> hipError_t {
     using L = decltype(lat);
     using R = decltype(rtag);
     hipLaunchKernelGGL((k_adj_init_grad<L, R>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const R*)lam,
-                       flags, has_mask, (const R*)init_fields, dL_du0, dL_drho0, field_dtype, g);
+                       flags, has_mask, layout, (const R*)init_fields, dL_du0, dL_drho0, field_dtype, g);
     return hipGetLastError();
   };
   const bool dbl = dtype == 0;

@@ -59,11 +59,6 @@ __device__ __forceinline__ void st_any(void* p, size_t i, double v, int field_dt
     ((float*)p)[i] = (float)v;
 }
 
-template <class T>
-__device__ __forceinline__ void store_from_double(T* p, double v) {
-  *p = static_cast<T>(v);
-}
-
 // Block-wide sum of `v` for every component; result valid in thread 0.
 template <int W>
 __device__ __forceinline__ void block_sum(double (&v)[W]) {
@@ -87,66 +82,6 @@ __device__ __forceinline__ void block_sum(double (&v)[W]) {
   }
 }
 
-
-// --------------------------------------------------------------- layouts
-// Where the post-collision populations P^t(x, q) of the stored state live:
-//   0  two-array pattern: slot (x, q);
-//   1  AA, after an even kernel: slot (x, opp q);
-//   2  AA, after an odd kernel or after initialisation: slot (x + c_q, q),
-//      or (x, opp q) when x + c_q is solid.
-// Solid cells keep their own slots (x, q) in every layout.
-//   In layout 2 a bounced slot holds the re-entering population, i.e. the
-//   outgoing one plus the moving-wall term, which is removed / added here.
-template <class L, class T>
-__device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int has_mask, int layout,
-                                          const CellIdx& c, const Geo& g, double* v,
-                                          const typename Storage<T>::R* wall, double rho0) {
-  const size_t N = (size_t)g.N;
-  const bool solid = has_mask && (flags[c.cell] & 1);
-  if (layout == 0 || solid) {
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + q * N + c.cell);
-  } else if (layout == 1) {
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + opp<L>(q) * N + c.cell);
-  } else {
-    LBM_NEIGHBOURS(c, g)
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
-      v[q] = (double)Storage<T>::load((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d);
-      if (fs & 1) v[q] -= (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0);
-    }
-  }
-}
-
-template <class L, class T>
-__device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_mask, int layout, const CellIdx& c,
-                                           const Geo& g, const double* v, const typename Storage<T>::R* wall,
-                                           double rho0) {
-  const size_t N = (size_t)g.N;
-  const bool solid = has_mask && (flags[c.cell] & 1);
-  if (layout == 0 || solid) {
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, v[q]);
-  } else if (layout == 1) {
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) store_from_double(P + opp<L>(q) * N + c.cell, v[q]);
-  } else {
-    LBM_NEIGHBOURS(c, g)
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
-      if (fs & 1)
-        store_from_double(P + opp<L>(q) * N + c.cell,
-                          v[q] + (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0));
-      else
-        store_from_double(P + q * N + d, v[q]);
-    }
-  }
-}
 
 // --------------------------------------------------------------- flags
 // bit 0: solid (bits 1..7 then hold the wall type); for fluid cells bit 1:
@@ -275,7 +210,6 @@ __global__ __launch_bounds__(512) void k_conserved(const T* __restrict__ P, cons
                                                    int has_mask, int layout, double* __restrict__ partials, Geo g,
                                                    double rho0, const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
-  const size_t N = (size_t)g.N;
   double v[4] = {0, 0, 0, 0};
   if (c.valid && !(has_mask && (flags[c.cell] & 1))) {
     double pf[L::Q];
@@ -387,6 +321,35 @@ hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags,
                          has_mask, layout, in, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+      return hipGetLastError();
+    })
+  })
+}
+
+// --------------------------------------------------------------- relayout
+// Copy a stored state from `layout` into the two-array layout of another
+// buffer, in the storage type (the adjoint tape of the AA pattern).  With
+// resting walls every value is copied bit for bit; a moving-wall term is
+// taken off in FP64 and the result rounded once.
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_relayout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                  int has_mask, int layout, T* __restrict__ out, Geo g, double rho0,
+                                                  const typename Storage<T>::R* wall) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  const size_t N = (size_t)g.N;
+  double v[L::Q];
+  load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) store_from_double(out + q * N + c.cell, v[q]);
+}
+
+hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
+                           void* out, const Geo& g, const Params& p, hipStream_t s) {
+  LBM_STENCIL_SWITCH(stencil, {
+    LBM_DTYPE_SWITCH(dtype, {
+      hipLaunchKernelGGL((k_relayout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
+                         has_mask, layout, (T*)out, g, p.rho0, (const typename Storage<T>::R*)p.wall);
       return hipGetLastError();
     })
   })

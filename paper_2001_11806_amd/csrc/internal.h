@@ -54,6 +54,8 @@ hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t*
                            int layout, double* out, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
                            const double* in, const Geo& g, const Params& p, hipStream_t s);
+hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                           int layout, void* out, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes,
                          hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc,
@@ -62,16 +64,22 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 
 // adjoint (adjoint.hip)
 bool adjoint_supported(int stencil, int method);
+// `layout` (seed, init gradient) places lambda like the stored state of the
+// same time (0 two arrays, 1 / 2 AA); the forward state P read by the seed is
+// in that layout too.
 hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags,
-                               int has_mask, const void* force_y, const void* dL_drho,
+                               int has_mask, int layout, const void* force_y, const void* dL_drho,
                                const void* dL_du, int field_dtype, void* lam, double* partials,
                                const Geo& g, const Params& p, hipStream_t s);
-hipError_t launch_adjoint_sweep(int stencil, int dtype, const void* P, const uint8_t* flags,
-                                int has_mask, const void* force_y, const void* lam_in,
+// phase -1: two lambda arrays, lam_in -> lam_out; 0 / 1: adjoint of the AA
+// even / odd kernel, in place on lam_in (lam_out unused).  P is the forward
+// state of the reversed step in the two-array layout.
+hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
+                                int has_mask, const void* force_y, void* lam_in,
                                 void* lam_out, double* partials, const Geo& g, const Params& p,
                                 hipStream_t s);
 hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags,
-                                    int has_mask, const void* init_fields, void* dL_du0,
+                                    int has_mask, int layout, const void* init_fields, void* dL_du0,
                                     void* dL_drho0, int field_dtype, const Geo& g,
                                     const Params& p, hipStream_t s);
 hipError_t launch_store_init_fields(int dtype, const void* rho, const void* u, int field_dtype,

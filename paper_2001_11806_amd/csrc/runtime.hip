@@ -135,7 +135,6 @@ int32_t validate(const lbm_config* cfg) {
     if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
     if (!adjoint_supported(cfg->stencil, cfg->method) || !cfg->compressible)
       return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT method only");
-    if (cfg->pattern != 0) return fail(LBM_EUNSUPPORTED, "the adjoint needs the two-array pattern");
   }
   return LBM_OK;
 }
@@ -324,7 +323,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
     if ((st = alloc(&c->init_fields, 4 * N * rb, "initial fields")) != LBM_OK) return bail(st);
     if ((st = alloc((void**)&c->adj_acc, (size_t)nblk * 3 * sizeof(double), "dL/dF accumulators")) != LBM_OK)
       return bail(st);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < (cfg->pattern == 1 ? 1 : 2); ++i)   // AA: the adjoint runs in place too
       if ((st = alloc(&c->lam[i], (size_t)c->Q * N * rb, "adjoint state")) != LBM_OK) return bail(st);
   }
   hipError_t e;
@@ -456,9 +455,16 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
   }
   for (; i < n; ++i) {
     if (ctx->k > 0 && ctx->t < ctx->cfg.max_tape_steps && ctx->t % ctx->k == 0) {
+      // the tape holds two-array layout: the segment recompute and the
+      // adjoint gather read it with the two-array kernels
       char* slot = (char*)ctx->tape + (size_t)(ctx->t / ctx->k) * ctx->grid_bytes;
-      HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
-              "tape copy");
+      if (is_aa(ctx))
+        HIP_TRY(launch_relayout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask,
+                                layout_of(ctx), slot, ctx->g, ctx->p, ctx->stream),
+                "tape relayout");
+      else
+        HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
+                "tape copy");
     }
     int32_t st = step_once(ctx);
     if (st != LBM_OK) return st;
@@ -531,10 +537,11 @@ int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_d
   if (ctx->t > ctx->cfg.max_tape_steps)
     return fail(LBM_ESTATE, "%lld steps exceed max_tape_steps = %d", (long long)ctx->t, ctx->cfg.max_tape_steps);
   const size_t lam_bytes = (size_t)ctx->Q * (size_t)ctx->g.N * compute_bytes(ctx->cfg.dtype);
-  HIP_TRY(launch_fill_zero(ctx->lam[1], lam_bytes, ctx->stream), "adjoint state clear");
+  if (!is_aa(ctx)) HIP_TRY(launch_fill_zero(ctx->lam[1], lam_bytes, ctx->stream), "adjoint state clear");
+  // the seed writes every slot of lam[0], in the layout of the current state
   HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
-                              ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0], ctx->adj_acc, ctx->g,
-                              ctx->p, ctx->stream),
+                              layout_of(ctx), ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0],
+                              ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
           "adjoint seed launch");
   ctx->lam_cur = 0;
   ctx->adj_T = ctx->t;
@@ -581,11 +588,17 @@ int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
     const void* P = nullptr;
     int32_t st = forward_state(ctx, s, &P);
     if (st != LBM_OK) return st;
-    HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, P, ctx->flags, ctx->has_mask, ctx->force,
-                                 ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->adj_acc, ctx->g, ctx->p,
-                                 ctx->stream),
-            "adjoint sweep launch");
-    ctx->lam_cur ^= 1;
+    if (is_aa(ctx)) {   // adjoint of the even (s even) or odd kernel, in place
+      HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags, ctx->has_mask,
+                                   ctx->force, ctx->lam[0], nullptr, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
+              "AA adjoint sweep launch");
+    } else {
+      HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, -1, P, ctx->flags, ctx->has_mask, ctx->force,
+                                   ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->adj_acc, ctx->g,
+                                   ctx->p, ctx->stream),
+              "adjoint sweep launch");
+      ctx->lam_cur ^= 1;
+    }
     ctx->adj_t -= 1;
   }
   return LBM_OK;
@@ -598,8 +611,8 @@ int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev, in
   if (ctx->adj_t != 0) return fail(LBM_ESTATE, "the adjoint has not reached t = 0");
   if (dL_du0_dev || dL_drho0_dev)
     HIP_TRY(launch_adjoint_init_grad(ctx->cfg.stencil, ctx->cfg.dtype, ctx->lam[ctx->lam_cur], ctx->flags,
-                                     ctx->has_mask, ctx->init_fields, dL_du0_dev, dL_drho0_dev, field_dtype, ctx->g,
-                                     ctx->p, ctx->stream),
+                                     ctx->has_mask, is_aa(ctx) ? 2 : 0, ctx->init_fields, dL_du0_dev, dL_drho0_dev,
+                                     field_dtype, ctx->g, ctx->p, ctx->stream),
             "init gradient launch");
   if (dL_dF) {
     HIP_TRY(launch_sum_partials(ctx->adj_acc, num_blocks(ctx->g), 3, ctx->acc, 0, ctx->stream), "dL/dF reduction");

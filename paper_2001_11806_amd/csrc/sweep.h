@@ -271,6 +271,71 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
   }
 }
 
+template <class T>
+__device__ __forceinline__ void store_from_double(T* p, double v) {
+  *p = static_cast<T>(v);
+}
+
+// ------------------------------------------------------------------ layouts
+// Where the post-collision populations P^t(x, q) of the stored state live:
+//   0  two-array pattern: slot (x, q);
+//   1  AA, after an even kernel: slot (x, opp q);
+//   2  AA, after an odd kernel or after initialisation: slot (x + c_q, q),
+//      or (x, opp q) when x + c_q is solid.
+// Solid cells keep their own slots (x, q) in every layout.
+//   In layout 2 a bounced slot holds the re-entering population, i.e. the
+//   outgoing one plus the moving-wall term, which is removed / added here.
+template <class L, class T>
+__device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int has_mask, int layout,
+                                          const CellIdx& c, const Geo& g, double* v,
+                                          const typename Storage<T>::R* wall, double rho0) {
+  const size_t N = (size_t)g.N;
+  const bool solid = has_mask && (flags[c.cell] & 1);
+  if (layout == 0 || solid) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + q * N + c.cell);
+  } else if (layout == 1) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + opp<L>(q) * N + c.cell);
+  } else {
+    LBM_NEIGHBOURS(c, g)
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
+      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      v[q] = (double)Storage<T>::load((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d);
+      if (fs & 1) v[q] -= (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0);
+    }
+  }
+}
+
+template <class L, class T>
+__device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_mask, int layout, const CellIdx& c,
+                                           const Geo& g, const double* v, const typename Storage<T>::R* wall,
+                                           double rho0) {
+  const size_t N = (size_t)g.N;
+  const bool solid = has_mask && (flags[c.cell] & 1);
+  if (layout == 0 || solid) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, v[q]);
+  } else if (layout == 1) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) store_from_double(P + opp<L>(q) * N + c.cell, v[q]);
+  } else {
+    LBM_NEIGHBOURS(c, g)
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
+      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      if (fs & 1)
+        store_from_double(P + opp<L>(q) * N + c.cell,
+                          v[q] + (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0));
+      else
+        store_from_double(P + q * N + d, v[q]);
+    }
+  }
+}
+
 // phase -1: two-array sweep src -> dst; phase 0 / 1: AA even / odd kernel on src.
 template <class L, int M, class T>
 hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags, const void* force_y, const Geo& g,

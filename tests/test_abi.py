@@ -78,7 +78,7 @@ def _create(lib, **kw):
     (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 2.2, 1, 1)), B.EINVAL, "omega_hi[1]"),
     (dict(method="CUMULANT", stencil="D3Q27", compressible=False), B.EUNSUPPORTED, "compressible"),
     (dict(pattern=2), B.EINVAL, "pattern"),
-    (dict(pattern=1, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "two-array pattern"),
+    (dict(pattern=1, method="TRT", magic=3 / 16, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
     (dict(launch_mode=3), B.EINVAL, "launch_mode"),
     (dict(cs_smag=-0.1), B.EINVAL, "cs_smag"),
     (dict(method="TRT", magic=3 / 16, cs_smag=0.1), B.EUNSUPPORTED, "Smagorinsky"),
