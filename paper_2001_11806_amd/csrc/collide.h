@@ -504,39 +504,142 @@ __device__ __forceinline__ void collide_mrt_gs(R* f, const R* F, const CollidePa
 // central moments are Gaussian (Isserlis): c_200 = K_xx,
 // c_220 = K_xx K_yy + 2 K_xy^2, c_211 = K_xx K_yz + 2 K_xy K_xz, c_222 = ...,
 // all odd ones zero.  Moments with exponents <= 2 per axis map back to
-// populations by a per-axis 3-point transform (central -> raw -> f).
+// populations by a per-axis 3-point transform about the mean u_a.
 // Second-order cumulants: K = Pi/rho - u u^T; shear part (off-diagonal and
 // traceless diagonal) relaxes with omega, the trace with omega_b, towards the
 // Maxwellian value c_s^2 I.
-// Numerically, K* = c_s^2 I + Dv and the result is assembled as
-//   f*_q - w_q rho_0 = drho prod phi + rho_0 (prod phi - prod w) + rho T_u[dc]
-// with the factorised equilibrium phi_a(c) (the Gaussian for Dv = 0) and dc
-// the central-moment deviations caused by Dv, so only small quantities are
-// formed in FP32.
+//
+// Arithmetic layout (all in the compute type, on small quantities only):
+//   - the ten raw moments of order <= 2 come from per-axis 3-point sums of
+//     the shifted populations (x, then y, then z), sharing partial sums;
+//   - K* = c_s^2 I + Dv; the central moments are C* = C_w + dC with C_w the
+//     lattice-weight moments (a product of (1, 0, c_s^2) per axis) and dC
+//     the small deviations;
+//   - the back-transform is done in deviation form, one axis at a time:
+//     E_1 = T_z(u_z)[dC] + (T_z(u_z) - T_z(0))[C_w], then the same along y
+//     and x, where (T(v) - T(0)) of (1, 0, c_s^2) is the 1-D equilibrium
+//     deviation dphi(v) = ((v^2 - v)/2, -v^2, (v^2 + v)/2); the result
+//     E_3 = T_u[C*] - w, so f*_q - w_q rho_0 = rho E_3 + drho w_q (the last
+//     pass carries the factor rho and the drho w_q term);
+//   - zero entries of dC are skipped explicitly (the compiler may not fold
+//     x * 0 under IEEE rules).
+
+// Per-axis coefficients of the central-moment -> population transform with
+// mean v, scaled by s: for the central moments (k0, k1, k2) about v,
+//   f(-1) = s [(v^2 - v)/2 k0 + (v - 1/2) k1 + k2/2]
+//   f( 0) = s [(1 - v^2) k0 - 2 v k1 - k2]
+//   f(+1) = s [(v^2 + v)/2 k0 + (v + 1/2) k1 + k2/2]
+template <class R>
+struct CmAxis {
+  R am, a0, ap, bm, b0, bp, h, m;  // k0 and k1 coefficients; k2 coefficients s/2 and -s
+  R dm, dz, dp;                    // s dphi(v)
+};
+
+template <class R>
+__device__ __forceinline__ CmAxis<R> cm_axis(R v, R s) {
+  CmAxis<R> a;
+  const R v2 = v * v;
+  const R hs = R(0.5) * s;
+  a.dm = hs * (v2 - v);
+  a.dz = -s * v2;
+  a.dp = hs * (v2 + v);
+  a.am = a.dm;
+  a.a0 = s - s * v2;
+  a.ap = a.dp;
+  a.bm = s * v - hs;
+  a.b0 = R(-2) * s * v;
+  a.bp = s * v + hs;
+  a.h = hs;
+  a.m = -s;
+  return a;
+}
+
+// dense line: outputs (f(-1), f(0), f(+1)) into o[0..2]
+template <class R>
+__device__ __forceinline__ void cm_line(const CmAxis<R>& a, R k0, R k1, R k2, R* o) {
+  const R hk2 = a.h * k2;
+  o[0] = a.am * k0 + (a.bm * k1 + hk2);
+  o[1] = a.a0 * k0 + (a.b0 * k1 + a.m * k2);
+  o[2] = a.ap * k0 + (a.bp * k1 + hk2);
+}
+// unscaled lines with a zero pattern (s = 1)
+template <class R>
+__device__ __forceinline__ void cm_line_k1(const CmAxis<R>& a, R k1, R* o) {
+  o[0] = a.bm * k1;
+  o[1] = a.b0 * k1;
+  o[2] = a.bp * k1;
+}
+template <class R>
+__device__ __forceinline__ void cm_line_k0k2(const CmAxis<R>& a, R k0, R k2, R* o) {
+  const R hk2 = R(0.5) * k2;
+  o[0] = a.am * k0 + hk2;
+  o[1] = a.a0 * k0 - k2;
+  o[2] = a.ap * k0 + hk2;
+}
+// the same plus cw dphi(v), the image of the weight moments cw (1, 0, c_s^2)
+// (each term formed separately: nothing of size cw is added and removed)
+template <class R>
+__device__ __forceinline__ void cm_line_k0k2_w(const CmAxis<R>& a, R k0, R k2, R cw, R* o) {
+  const R hk2 = R(0.5) * k2;
+  o[0] = a.am * k0 + (cw * a.dm + hk2);
+  o[1] = a.a0 * k0 + (cw * a.dz - k2);
+  o[2] = a.ap * k0 + (cw * a.dp + hk2);
+}
+
 template <class L, class R>
 __device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const CollideParams<R>& p) {
   constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
   constexpr R cs2 = R(1.0 / 3.0);
-  R drho, jx, jy, jz;
-  density_momentum<L>(f, drho, jx, jy, jz);
-  R Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+  constexpr R w1[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  // ---- raw moments of order <= 2 by per-axis sums; index i = c + 1
+  R X0[3][NK], X1[3][NK], X2[3][NK];   // x pass: sum, f+ - f-, f+ + f- along x
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
-    if (cx != 0) Pxx += f[q];
-    if (cy != 0) Pyy += f[q];
-    if (cz != 0) Pzz += f[q];
-    if (cx * cy == 1) Pxy += f[q];
-    if (cx * cy == -1) Pxy -= f[q];
-    if (cx * cz == 1) Pxz += f[q];
-    if (cx * cz == -1) Pxz -= f[q];
-    if (cy * cz == 1) Pyz += f[q];
-    if (cy * cz == -1) Pyz -= f[q];
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int z = D == 3 ? k - 1 : 0;
+      const R a = f[qindex<L>(-1, j - 1, z)], b = f[qindex<L>(0, j - 1, z)], c = f[qindex<L>(1, j - 1, z)];
+      X2[j][k] = c + a;
+      X1[j][k] = c - a;
+      X0[j][k] = X2[j][k] + b;
+    }
+  R Y00[NK], Y01[NK], Y02[NK], Y10[NK], Y11[NK], Y20[NK];  // y pass, moments x^a y^b
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    Y02[k] = X0[2][k] + X0[0][k];
+    Y01[k] = X0[2][k] - X0[0][k];
+    Y00[k] = Y02[k] + X0[1][k];
+    Y11[k] = X1[2][k] - X1[0][k];
+    Y10[k] = (X1[2][k] + X1[0][k]) + X1[1][k];
+    Y20[k] = (X2[2][k] + X2[0][k]) + X2[1][k];
+  }
+  R drho, jx, jy, jz = R(0), Pxx, Pyy, Pzz = R(0), Pxy, Pxz = R(0), Pyz = R(0);
+  if constexpr (D == 3) {   // z pass
+    const R m002 = Y00[2] + Y00[0];
+    jz = Y00[2] - Y00[0];
+    drho = m002 + Y00[1];
+    Pzz = m002;
+    jy = (Y01[2] + Y01[0]) + Y01[1];
+    Pyz = Y01[2] - Y01[0];
+    jx = (Y10[2] + Y10[0]) + Y10[1];
+    Pxz = Y10[2] - Y10[0];
+    Pyy = (Y02[2] + Y02[0]) + Y02[1];
+    Pxx = (Y20[2] + Y20[0]) + Y20[1];
+    Pxy = (Y11[2] + Y11[0]) + Y11[1];
+  } else {
+    drho = Y00[0];
+    jx = Y10[0];
+    jy = Y01[0];
+    Pxx = Y20[0];
+    Pyy = Y02[0];
+    Pxy = Y11[0];
   }
   const R rho = p.rho0 + drho;
   const R inv = R(1) / rho;
   const R u[3] = {jx * inv, jy * inv, jz * inv};
-  // non-equilibrium second cumulants (shift: sum c_a c_b w rho_0 = c_s^2 rho_0 delta)
+  // ---- relaxed second-order cumulant deviations from c_s^2 I
+  // (shift: sum c_a c_b w rho_0 = c_s^2 rho_0 delta)
   const R Kxx = (Pxx - drho * cs2) * inv - u[0] * u[0];
   const R Kyy = (Pyy - drho * cs2) * inv - u[1] * u[1];
   const R Kzz = (D == 3) ? (Pzz - drho * cs2) * inv - u[2] * u[2] : R(0);
@@ -544,103 +647,93 @@ __device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const Col
   const R ks = R(1) - p.om, kb = R(1) - p.om_b;
   const R Dxx = ks * (Kxx - tr) + kb * tr;
   const R Dyy = ks * (Kyy - tr) + kb * tr;
-  const R Dzz = (D == 3) ? ks * (Kzz - tr) + kb * tr : R(0);
   const R Dxy = ks * (Pxy * inv - u[0] * u[1]);
-  const R Dxz = (D == 3) ? ks * (Pxz * inv - u[0] * u[2]) : R(0);
-  const R Dyz = (D == 3) ? ks * (Pyz * inv - u[1] * u[2]) : R(0);
-  // central-moment deviations dc[a][b][c]
-  constexpr int NK = (D == 3) ? 3 : 1;
-  R c[3][3][NK];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < NK; ++k) c[i][j][k] = R(0);
-  c[2][0][0] = Dxx;
-  c[0][2][0] = Dyy;
-  c[1][1][0] = Dxy;
-  c[2][2][0] = cs2 * (Dxx + Dyy) + Dxx * Dyy + R(2) * Dxy * Dxy;
+  // ---- back-transform in deviation form
+  const CmAxis<R> ay = cm_axis<R>(u[1], R(1));
+  const CmAxis<R> ax = cm_axis<R>(u[0], rho);   // last pass carries rho
+  // per-x-population term of the last pass: rho dphi_x + drho w1
+  const R gx[3] = {ax.dm + drho * w1[0], ax.dz + drho * w1[1], ax.dp + drho * w1[2]};
   if constexpr (D == 3) {
-    c[0][0][NK - 1] = Dzz;
-    c[1][0][NK > 1 ? 1 : 0] = Dxz;
-    c[0][1][NK > 1 ? 1 : 0] = Dyz;
-    c[2][0][NK - 1] = cs2 * (Dxx + Dzz) + Dxx * Dzz + R(2) * Dxz * Dxz;
-    c[0][2][NK - 1] = cs2 * (Dyy + Dzz) + Dyy * Dzz + R(2) * Dyz * Dyz;
-    c[2][1][NK > 1 ? 1 : 0] = (cs2 + Dxx) * Dyz + R(2) * Dxy * Dxz;
-    c[1][2][NK > 1 ? 1 : 0] = (cs2 + Dyy) * Dxz + R(2) * Dxy * Dyz;
-    c[1][1][NK - 1] = (cs2 + Dzz) * Dxy + R(2) * Dxz * Dyz;
-    c[2][2][NK - 1] = cs2 * cs2 * (Dxx + Dyy + Dzz) + cs2 * (Dxx * Dyy + Dxx * Dzz + Dyy * Dzz) +
-                      Dxx * Dyy * Dzz + R(2) * (cs2 + Dxx) * Dyz * Dyz + R(2) * (cs2 + Dyy) * Dxz * Dxz +
-                      R(2) * (cs2 + Dzz) * Dxy * Dxy + R(8) * Dxy * Dxz * Dyz;
-  }
-  // per-axis central -> population transform with mean u_a:
-  // f(0) = k0 (1 - u^2) - 2u k1 - k2, f(+-1) = (k0 (u^2 +- u) + k1 (2u +- 1) + k2) / 2
-  if constexpr (D == 3) {
-    const R v = u[2], v2 = v * v;
+    const R Dzz = ks * (Kzz - tr) + kb * tr;
+    const R Dxz = ks * (Pxz * inv - u[0] * u[2]);
+    const R Dyz = ks * (Pyz * inv - u[1] * u[2]);
+    // nonzero central-moment deviations beyond order 2 (Isserlis)
+    const R c220 = cs2 * (Dxx + Dyy) + Dxx * Dyy + R(2) * Dxy * Dxy;
+    const R c202 = cs2 * (Dxx + Dzz) + Dxx * Dzz + R(2) * Dxz * Dxz;
+    const R c022 = cs2 * (Dyy + Dzz) + Dyy * Dzz + R(2) * Dyz * Dyz;
+    const R c211 = (cs2 + Dxx) * Dyz + R(2) * Dxy * Dxz;
+    const R c121 = (cs2 + Dyy) * Dxz + R(2) * Dxy * Dyz;
+    const R c112 = (cs2 + Dzz) * Dxy + R(2) * Dxz * Dyz;
+    const R c222 = cs2 * cs2 * (Dxx + Dyy + Dzz) + cs2 * (Dxx * Dyy + Dxx * Dzz + Dyy * Dzz) + Dxx * Dyy * Dzz +
+                   R(2) * (cs2 + Dxx) * Dyz * Dyz + R(2) * (cs2 + Dyy) * Dxz * Dxz +
+                   R(2) * (cs2 + Dzz) * Dxy * Dxy + R(8) * Dxy * Dxz * Dyz;
+    const CmAxis<R> az = cm_axis<R>(u[2], R(1));
+    // pass z: E[i][j][kk], i, j exponents in x, y; kk population in z.
+    // C_w lines (i, j in {0, 2}) add cw_i cw_j dphi_z.
+    R E[3][3][3];
+    {
+      const R hz = R(0.5) * Dzz;   // line (0, 0): (0, 0, Dzz) + dphi_z
+      E[0][0][0] = hz + az.dm;
+      E[0][0][1] = az.dz - Dzz;
+      E[0][0][2] = hz + az.dp;
+    }
+    cm_line_k1(az, Dyz, E[0][1]);
+    cm_line_k1(az, Dxz, E[1][0]);
+    cm_line_k1(az, c121, E[1][2]);
+    cm_line_k1(az, c211, E[2][1]);
+    cm_line_k0k2(az, Dxy, c112, E[1][1]);
+    cm_line_k0k2_w(az, Dyy, c022, cs2, E[0][2]);
+    cm_line_k0k2_w(az, Dxx, c202, cs2, E[2][0]);
+    cm_line_k0k2_w(az, c220, c222, cs2 * cs2, E[2][2]);
+    // pass y: lines (i, kk) over the y exponent; C_w rows i in {0, 2} add
+    // cw_i w1_kk dphi_y
+    R G[3][3][3];   // G[i][jj][kk]
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const R k0 = c[i][j][0], k1 = c[i][j][NK > 1 ? 1 : 0], k2 = c[i][j][NK - 1];
-        c[i][j][0] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
-        c[i][j][NK > 1 ? 1 : 0] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
-        c[i][j][NK - 1] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
-      }
-  }
-  {
-    const R v = u[1], v2 = v * v;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        const R k0 = c[i][0][k], k1 = c[i][1][k], k2 = c[i][2][k];
-        c[i][0][k] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
-        c[i][1][k] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
-        c[i][2][k] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
-      }
-  }
-  {
-    const R v = u[0], v2 = v * v;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        const R k0 = c[0][j][k], k1 = c[1][j][k], k2 = c[2][j][k];
-        c[0][j][k] = R(0.5) * (k0 * (v2 - v) + k1 * (R(2) * v - R(1)) + k2);
-        c[1][j][k] = k0 * (R(1) - v2) - R(2) * v * k1 - k2;
-        c[2][j][k] = R(0.5) * (k0 * (v2 + v) + k1 * (R(2) * v + R(1)) + k2);
-      }
-  }
-  // factorised equilibrium phi = w1 + dphi per axis
-  R w1[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
-  R ph[3][3], dph[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const R v = u[a], v2 = v * v;
-    dph[a][0] = R(0.5) * (v2 - v);
-    dph[a][1] = -v2;
-    dph[a][2] = R(0.5) * (v2 + v);
-#pragma unroll
-    for (int s = 0; s < 3; ++s) ph[a][s] = w1[s] + dph[a][s];
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
-        R prod, dprod;
-        if constexpr (D == 3) {
-          prod = ph[0][i] * ph[1][j] * ph[2][k];
-          dprod = dph[0][i] * ph[1][j] * ph[2][k] + w1[i] * dph[1][j] * ph[2][k] + w1[i] * w1[j] * dph[2][k];
-        } else {
-          prod = ph[0][i] * ph[1][j];
-          dprod = dph[0][i] * ph[1][j] + w1[i] * dph[1][j];
+      for (int kk = 0; kk < 3; ++kk) {
+        R o[3];
+        cm_line(ay, E[i][0][kk], E[i][1][kk], E[i][2][kk], o);
+        if (i != 1) {
+          const R cw = (i == 0 ? R(1) : cs2) * w1[kk];
+          o[0] += cw * ay.dm;
+          o[1] += cw * ay.dz;
+          o[2] += cw * ay.dp;
         }
-        f[q] = drho * prod + p.rho0 * dprod + rho * c[i][j][k];
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) G[i][jj][kk] = o[jj];
       }
+    // pass x (scaled by rho) plus (rho dphi_x + drho w1) w1_jj w1_kk
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        R o[3];
+        cm_line(ax, G[0][jj][kk], G[1][jj][kk], G[2][jj][kk], o);
+        const R ww = w1[jj] * w1[kk];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) f[qindex<L>(ii - 1, jj - 1, kk - 1)] = o[ii] + gx[ii] * ww;
+      }
+  } else {
+    const R c220 = cs2 * (Dxx + Dyy) + Dxx * Dyy + R(2) * Dxy * Dxy;
+    // pass y: lines over i (x exponent): (0, 0, Dyy) + dphi_y, (0, Dxy, 0), (Dxx, 0, c220) + c_s^2 dphi_y
+    R G[3][3];
+    {
+      const R hy = R(0.5) * Dyy;
+      G[0][0] = hy + ay.dm;
+      G[0][1] = ay.dz - Dyy;
+      G[0][2] = hy + ay.dp;
+    }
+    cm_line_k1(ay, Dxy, G[1]);
+    cm_line_k0k2_w(ay, Dxx, c220, cs2, G[2]);
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      R o[3];
+      cm_line(ax, G[0][jj], G[1][jj], G[2][jj], o);
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) f[qindex<L>(ii - 1, jj - 1, 0)] = o[ii] + gx[ii] * w1[jj];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- cumulant, general rates
