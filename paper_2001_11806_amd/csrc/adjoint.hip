@@ -204,7 +204,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, cons
   if (c.valid && !(fl & 1)) {
     R f[L::Q];
     uint32_t bb = 0;
-    gather<L, T>(P, flags, fl, c, g, f, &bb, p.wall, p.rho0);
+    gather<L, T>(P, flags, fl, c, g, f, &bb, p);
     R lam[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, c
   if (c.valid && !(fl & 1)) {
     R f[L::Q];
     uint32_t bb = 0;   // bit q: x - c_q is solid (so x + c_opp(q) is solid)
-    gather<L, T>(P, flags, fl, c, g, f, &bb, p.wall, p.rho0);
+    gather<L, T>(P, flags, fl, c, g, f, &bb, p);
     LBM_NEIGHBOURS(c, g)
     const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(R), (uint32_t)c.x * (uint32_t)sizeof(R),
                             (uint32_t)xm * (uint32_t)sizeof(R)};  // x - c_x for c_x = -1, 0, +1

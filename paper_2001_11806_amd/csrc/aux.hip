@@ -85,27 +85,31 @@ __device__ __forceinline__ void block_sum(double (&v)[W]) {
 
 // --------------------------------------------------------------- flags
 // bit 0: solid (bits 1..7 then hold the wall type); for fluid cells bit 1:
-// at least one solid upstream neighbour.
+// at least one solid upstream neighbour.  links: for fluid cells bit q set
+// when x - c_q is solid (the links the sweep bounces back), else 0.
 template <class L>
 __global__ __launch_bounds__(512) void k_build_flags(const uint8_t* __restrict__ solid, uint8_t* __restrict__ flags,
-                                                     Geo g) {
+                                                     uint32_t* __restrict__ links, Geo g) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   LBM_NEIGHBOURS(c, g)
   // solid cells: bit 0 set, bits 1..7 = wall type (the mask value)
   uint8_t f = solid[c.cell] ? (uint8_t)(1u | ((unsigned)solid[c.cell] << 1)) : 0;
+  uint32_t m = 0;
   if (!f) {
-    bool near = false;
 #pragma unroll
-    for (int q = 1; q < L::Q; ++q) near |= solid[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] != 0;
-    if (near) f |= 2;
+    for (int q = 1; q < L::Q; ++q)
+      if (solid[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] != 0) m |= 1u << q;
+    if (m) f |= 2;
   }
   flags[c.cell] = f;
+  links[c.cell] = m;
 }
 
-hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, const Geo& g, hipStream_t s) {
+hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, uint32_t* links, const Geo& g,
+                              hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
-    hipLaunchKernelGGL(k_build_flags<L>, dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, solid, flags, g);
+    hipLaunchKernelGGL(k_build_flags<L>, dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, solid, flags, links, g);
     return hipGetLastError();
   })
 }

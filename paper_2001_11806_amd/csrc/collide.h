@@ -27,7 +27,9 @@ struct CollideParams {
   R hi[4];    // orders 3..6
   R smag18;   // 18 C_S^2
   int compressible;
-  const R* wall;  // wall velocity table [128][3]
+  const R* wall;          // wall velocity table [128][3]
+  const uint32_t* links;  // per cell: bit q set when x - c_q is solid (cells next to a wall)
+  int moving;             // the mask holds moving-wall types (values >= 2)
 };
 
 

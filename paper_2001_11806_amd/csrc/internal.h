@@ -25,6 +25,8 @@ struct Params {
   double smag18;   // 18 C_S^2 (Smagorinsky), 0 = off
   int compressible;
   const void* wall; // device table [128][3] of wall velocities (compute type), row = wall id
+  const uint32_t* links;  // per-cell bounced-link bits (NULL without a mask)
+  int moving;             // the mask holds moving-wall types
 };
 
 inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
@@ -37,8 +39,9 @@ hipError_t launch_sweep(int stencil, int method, int dtype, int phase, const voi
 bool sweep_supported(int stencil, int method);
 
 // auxiliary (aux.hip)
-hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, const Geo& g,
-                              hipStream_t s);
+// flags (one byte per cell) and the bounced-link bits of every cell
+hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags, uint32_t* links,
+                              const Geo& g, hipStream_t s);
 // layout of the stored state: 0 two-array; 1 AA after an even kernel;
 // 2 AA streamed (after an odd kernel or initialisation)
 hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,

@@ -50,6 +50,7 @@ struct lbm_ctx {
   void* grid[2] = {nullptr, nullptr};
   int cur = 0;
   uint8_t* flags = nullptr;
+  uint32_t* links = nullptr;   // bounced-link bits per cell (with a mask)
   int has_mask = 0;
   void* force = nullptr;       // compute type, 3 * ny
   void* wall = nullptr;        // compute type, [128][3] wall velocities by wall type
@@ -83,8 +84,8 @@ void free_ctx(lbm_ctx* c) {
   for (auto& ge : c->graph_exec)
     if (ge) (void)hipGraphExecDestroy(ge);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->force, c->wall, c->partials, c->acc, c->adj_acc, c->tape,
-                  c->seg,     c->init_fields, c->lam[0], c->lam[1]};
+  void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->links, c->force,       c->wall,   c->partials, c->acc,
+                  c->adj_acc, c->tape,    c->seg,   c->init_fields, c->lam[0], c->lam[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete c;
@@ -152,7 +153,7 @@ Geo make_geo(const lbm_config& c) {
 }
 
 Params make_params(const lbm_config& c) {
-  Params p;
+  Params p{};
   p.rho0 = c.rho0;
   p.om = c.rates.omega;
   p.om_b = c.rates.omega_bulk;
@@ -280,11 +281,14 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   *out = nullptr;
   int32_t st = validate(cfg);
   if (st != LBM_OK) return st;
+  int moving = 0;
   if (solid_mask_host) {
     const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
-    for (size_t i = 0; i < n; ++i)
+    for (size_t i = 0; i < n; ++i) {
       if (solid_mask_host[i] > 127)
         return fail(LBM_EINVAL, "mask value %d at cell %zu: wall types are 1..127", solid_mask_host[i], i);
+      moving |= solid_mask_host[i] >= 2;
+    }
   }
   lbm_ctx* c = new lbm_ctx();
   c->cfg = *cfg;
@@ -297,6 +301,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   }
   c->g = make_geo(*cfg);
   c->p = make_params(*cfg);
+  c->p.moving = moving;
   c->stream = (hipStream_t)hip_stream;
   const size_t N = (size_t)c->g.N;
   c->grid_bytes = (size_t)c->Q * N * storage_bytes(cfg->dtype);
@@ -336,10 +341,12 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   if (solid_mask_host) {
     c->has_mask = 1;
     if ((st = alloc((void**)&c->flags, N, "flag field")) != LBM_OK) return bail(st);
+    if ((st = alloc((void**)&c->links, N * sizeof(uint32_t), "bounced-link bits")) != LBM_OK) return bail(st);
+    c->p.links = c->links;
     uint8_t* solid_dev = nullptr;
     if ((st = alloc((void**)&solid_dev, N, "solid mask staging")) != LBM_OK) return bail(st);
     e = hipMemcpy(solid_dev, solid_mask_host, N, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_build_flags(cfg->stencil, solid_dev, c->flags, c->g, c->stream);
+    if (e == hipSuccess) e = launch_build_flags(cfg->stencil, solid_dev, c->flags, c->links, c->g, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(solid_dev);
     if (e != hipSuccess) return bail(hip_fail(e, "solid mask upload"));

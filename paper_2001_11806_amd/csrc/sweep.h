@@ -41,6 +41,8 @@ inline CollideParams<R> to_collide_params(const Params& p) {
   c.smag18 = R(p.smag18);
   c.compressible = p.compressible;
   c.wall = (const R*)p.wall;
+  c.links = p.links;
+  c.moving = p.moving;
   return c;
 }
 
@@ -108,12 +110,14 @@ __device__ __forceinline__ const T* row_base(const T* src, int q, int y, int z, 
 // Pull-gather of the Q pre-collision populations of one fluid cell with
 // halfway bounce-back.  Every link first loads its upstream slot (for a
 // bounced link that slot belongs to a solid cell: in bounds, value unused);
-// cells next to a wall (flag bit 1) then replace the bounced links by their
-// own outgoing population opp(q).  Bit q of *bb is set for bounced links.
+// cells next to a wall (flag bit 1) then read their bounced-link bits and
+// replace those links by their own outgoing population opp(q), plus the
+// moving-wall term (wall type from the solid neighbour's flag byte) when the
+// mask has moving walls.  Bit q of *bb is set for bounced links.
 template <class L, class T>
 __device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t* __restrict__ flags, int fl,
                                        const CellIdx& c, const Geo& g, typename Storage<T>::R* f, uint32_t* bb,
-                                       const typename Storage<T>::R* wall, typename Storage<T>::R rho0) {
+                                       const CollideParams<typename Storage<T>::R>& p) {
   LBM_NEIGHBOURS(c, g)
   const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(T), (uint32_t)c.x * (uint32_t)sizeof(T),
                           (uint32_t)xm * (uint32_t)sizeof(T)};  // source x for c_x = -1, 0, +1
@@ -122,16 +126,13 @@ __device__ __forceinline__ void gather(const T* __restrict__ src, const uint8_t*
     f[q] = Storage<T>::load(at_bytes(row_base<L>(src, q, c.y, c.z, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]));
   uint32_t m = 0;
   if (fl & 2) {
+    m = p.links[c.cell];
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
-      const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
-      const int sx = cx > 0 ? xm : (cx < 0 ? xp : c.x);
-      const int sy = cy > 0 ? ym : (cy < 0 ? yp : c.y);
-      const int sz = cz > 0 ? zm : (cz < 0 ? zp : c.z);
-      const int fs = flags[(sz * g.ny + sy) * g.nx + sx];
-      if (fs & 1) {   // solid: bits 1..7 hold the wall type
-        f[q] = Storage<T>::load(src + (size_t)opp<L>(q) * (size_t)g.N + c.cell) + wall_term<L>(q, fs >> 1, wall, rho0);
-        m |= 1u << q;
+      if ((m >> q) & 1u) {
+        f[q] = Storage<T>::load(src + (size_t)opp<L>(q) * (size_t)g.N + c.cell);
+        if (p.moving)   // solid neighbour's flag byte: bits 1..7 hold the wall type
+          f[q] += wall_term<L>(q, flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] >> 1, p.wall, p.rho0);
       }
     }
   }
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
     if (fl & 1) return;  // solid cells are never updated
   }
   R f[L::Q];
-  gather<L, T>(src, flags, fl, c, g, f, nullptr, p.wall, p.rho0);
+  gather<L, T>(src, flags, fl, c, g, f, nullptr, p);
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
   store_cell<T, NT>(dst, c, g, f, L::Q);
@@ -243,11 +244,16 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
 #pragma unroll
   for (int q = 0; q < L::Q; ++q)
     f[q] = Storage<T>::load(at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]));
+  uint32_t m = 0;   // bit q: x - c_q is solid, i.e. x + c_opp(q) is solid
   if (fl & 2) {
+    m = p.links[c.cell];
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
-      const int fs = flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)];
-      if (fs & 1) f[q] = Storage<T>::load(A + (size_t)q * (size_t)g.N + c.cell) + wall_term<L>(q, fs >> 1, p.wall, p.rho0);
+      if ((m >> q) & 1u) {
+        f[q] = Storage<T>::load(A + (size_t)q * (size_t)g.N + c.cell);
+        if (p.moving)
+          f[q] += wall_term<L>(q, flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] >> 1, p.wall, p.rho0);
+      }
     }
   }
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
@@ -261,10 +267,14 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
     // opposite slot; solid cells' slots are never written
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      const int fs = q > 0 ? flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] : 0;
-      if (fs & 1)   // the population that re-enters along opp(q) carries the wall term
-        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, f[q] + wall_term<L>(opp<L>(q), fs >> 1, p.wall, p.rho0));
-      else
+      if (q > 0 && ((m >> opp<L>(q)) & 1u)) {   // x + c_q is solid
+        // the population that re-enters along opp(q) carries the wall term
+        R v = f[q];
+        if (p.moving)
+          v += wall_term<L>(opp<L>(q), flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] >> 1, p.wall,
+                            p.rho0);
+        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, v);
+      } else
         put<T, NT>(at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]),
                    f[q]);
     }
