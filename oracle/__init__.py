@@ -19,7 +19,8 @@ equilibrium  density/velocity (Eq. 2), discrete equilibrium (Eq. 3),
 moments      monomial moment bases, shear/bulk split, weighted
              Gram-Schmidt (Sec. III-A "Moment Space", III-C "MRT")
 collision    SRT (Eq. 1), TRT (Sec. III-C), MRT (Eq. 4),
-             cumulant (Eq. 9, Sec. III-B)
+             cumulant (Eq. 9, Sec. III-B), Smagorinsky (Eqs. 11-14),
+             entropic KBC (Sec. III-C "Entropic KBC Models")
 stream       pull streaming, halfway bounce-back (Sec. IV-B, Fig. stream-pull)
 run          initialisation, time stepping, readout, storage rounding
 adjoint      tangent-linear and discrete-adjoint maps of the SRT+Guo+bounce-back

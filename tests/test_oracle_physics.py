@@ -52,7 +52,8 @@ def test_taylor_green_c1_energy_decay():
 
 
 @pytest.mark.parametrize("name,method", [("D3Q19", "SRT"), ("D3Q19", "TRT"), ("D3Q27", "MRT"),
-                                          ("D3Q27", "CUMULANT"), ("D2Q9", "MRT"), ("D2Q9", "CUMULANT")])
+                                          ("D3Q27", "CUMULANT"), ("D2Q9", "MRT"), ("D2Q9", "CUMULANT"),
+                                          ("D2Q9", "KBC"), ("D3Q19", "KBC"), ("D3Q27", "KBC")])
 def test_shear_wave_viscosity(name, method):
     """A small shear wave u_y = A sin(k x) decays as exp(-nu k^2 t) with
     nu = c_s^2 (1/omega - 1/2) of the shear rate (paper, Eq. 14 at |S| = 0)."""
