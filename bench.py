@@ -278,9 +278,9 @@ def main():
 
 def bench_methods(torch, LBM, inputs, Timer, run_forward):
     """Per-method throughput on the same lattice (the paper compares TRT,
-    Smagorinsky, weighted MRT and cumulant kernels with the AA pattern and
-    finds them all memory bound): D3Q19 256^3 channel FP64 with AA, and
-    D3Q27 256^3 periodic FP32 two-array."""
+    Smagorinsky, weighted MRT, cumulant and entropic KBC kernels with the AA
+    pattern and finds them memory bound): D3Q19 256^3 channel FP64 with AA,
+    and D3Q27 256^3 periodic FP32 two-array."""
     out = {}
     n = 256
     mask, _, u = inputs.channel_flow(n, seed=2, amp=1e-3)
@@ -288,7 +288,7 @@ def bench_methods(torch, LBM, inputs, Timer, run_forward):
     base = dict(omega=1 / 0.8, omega_bulk=1.2, magic=3 / 16, omega_odd=0.0, omega_hi=(1.0,) * 4)
     for name, method, extra in (("SRT", "SRT", {}), ("TRT", "TRT", {}), ("MRT", "MRT", {}),
                                 ("SRT_Smagorinsky", "SRT", {"cs_smag": 0.1}),
-                                ("MRT_Smagorinsky", "MRT", {"cs_smag": 0.1})):
+                                ("MRT_Smagorinsky", "MRT", {"cs_smag": 0.1}), ("KBC", "KBC", {})):
         r = run_forward(torch, LBM, inputs, "D3Q19", method, "f64", (n, n, n), dict(base, **extra), mask, u, F=F,
                         steps=50, warmup=5, pattern=1, cs_smag=extra.get("cs_smag", 0.0))
         r.pop("u_out")
@@ -298,7 +298,8 @@ def bench_methods(torch, LBM, inputs, Timer, run_forward):
     for name, method, rates in (("SRT", "SRT", base), ("TRT", "TRT", base), ("MRT", "MRT", base),
                                 ("CUMULANT", "CUMULANT", dict(base, omega_bulk=1.0)),
                                 ("CUMULANT_general_rates", "CUMULANT", dict(base, omega_bulk=1.0,
-                                                                            omega_hi=(1.2, 1.1, 1.0, 1.3)))):
+                                                                            omega_hi=(1.2, 1.1, 1.0, 1.3))),
+                                ("KBC", "KBC", base)):
         r = run_forward(torch, LBM, inputs, "D3Q27", method, "f32", (n, n, n), rates, None, u27, steps=50, warmup=5)
         r.pop("u_out")
         out["D3Q27_f32_" + name] = {"mlups": r["mlups"], "GBps": r["achieved_GBps"]}

@@ -54,8 +54,9 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* stencils (Sec. III-A) */
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 };
-/* collision operators: Eq. (1); Sec. III-C TRT; Eq. (4); Eq. (9) */
-enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2, LBM_CUMULANT = 3 };
+/* collision operators: Eq. (1); Sec. III-C TRT; Eq. (4); Eq. (9); Sec. III-C
+ * "Entropic KBC Models" (MRT with a per-cell higher-order rate) */
+enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2, LBM_CUMULANT = 3, LBM_KBC = 4 };
 /* PDF storage type (FP64 computes in FP64, the others in FP32); also used
  * to describe caller field buffers (only LBM_F64 / LBM_F32 there) */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 };
@@ -72,8 +73,8 @@ enum {
 
 /* Relaxation rates (Sec. III-A "Relaxation rates"; runtime constants). */
 typedef struct {
-  double omega;       /* SRT omega = 1/tau; TRT even rate; MRT/cumulant shear rate */
-  double omega_bulk;  /* MRT/cumulant bulk rate (trace of the 2nd-order moments)   */
+  double omega;       /* SRT omega = 1/tau; TRT even rate; MRT/cumulant/KBC shear rate */
+  double omega_bulk;  /* MRT/cumulant/KBC bulk rate (trace of the 2nd-order moments) */
   double omega_odd;   /* TRT odd rate; if <= 0 it is derived from `magic`          */
   double magic;       /* TRT Lambda = (1/omega_even - 1/2)(1/omega_odd - 1/2)      */
   double omega_hi[4]; /* MRT/cumulant rates of moment orders 3, 4, 5, 6            */
@@ -85,7 +86,7 @@ typedef struct {
 
 typedef struct {
   int32_t stencil;          /* LBM_D2Q9 | LBM_D3Q19 | LBM_D3Q27                    */
-  int32_t method;           /* LBM_SRT | LBM_TRT | LBM_MRT | LBM_CUMULANT          */
+  int32_t method;           /* LBM_SRT | LBM_TRT | LBM_MRT | LBM_CUMULANT | LBM_KBC */
   int32_t dtype;            /* PDF storage type                                     */
   int32_t nx, ny, nz;       /* lattice size; nz == 1 for D2Q9; N < 2^31            */
   lbm_rates rates;          /* every used rate must lie in (0, 2)                   */
@@ -106,8 +107,13 @@ typedef struct {
  * 3..6 on D3Q27, orders 3 and 4 on D2Q9 and D3Q19);
  * CUMULANT on D2Q9 and D3Q27, compressible and without body force (higher-order
  * rates all 1 use a Gaussian-reconstruction kernel, other rates a general FP64
- * cumulant kernel); both patterns for every method; the adjoint tape for
- * compressible SRT with either pattern.  Others return LBM_EUNSUPPORTED. */
+ * cumulant kernel); KBC on all stencils (shear and bulk rates fixed, one
+ * entropic rate per cell for orders >= 3:
+ *   omega_h = 1 + [(1 - omega) <ds, dh>_E + (1 - omega_bulk) <db, dh>_E] / <dh, dh>_E,
+ *   <a, b>_E = sum_q a_q b_q / f^eq_q, ds / db / dh the shear, bulk and
+ *   higher-order parts of f - f^eq; omega_h = 1 when dh = 0);
+ * both patterns for every method; the adjoint tape for compressible SRT with
+ * either pattern.  Others return LBM_EUNSUPPORTED. */
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when
  * checkpoint_every > 0) and copies the solid mask in.

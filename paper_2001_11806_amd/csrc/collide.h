@@ -16,7 +16,7 @@ namespace lbm {
 
 // Internal method codes: the ABI's four, plus SRT and MRT with the
 // Smagorinsky model (local shear rate).
-enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5, M_CUMULANT_GEN = 6 };
+enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5, M_CUMULANT_GEN = 6, M_KBC = 7 };
 
 template <class R>
 struct CollideParams {
@@ -928,6 +928,124 @@ __device__ __forceinline__ void collide_cumulant_general(R* f, const R* /*F*/, c
       }
 }
 
+// ---------------------------------------------------------------- KBC
+// Entropic KBC-type collision (Sec. III-C "Entropic KBC Models"): an MRT
+// method in the lattice-weighted basis whose second-order moments relax with
+// fixed rates (shear omega, bulk omega_b) and whose moments of order >= 3
+// relax with one rate omega_h chosen per cell, from the entropy condition
+// with ln x ~ x - 1:
+//   omega_h = 1 + [(1 - omega) <ds, dh>_E + (1 - omega_b) <db, dh>_E] / <dh, dh>_E,
+//   <a, b>_E = sum_q a_q b_q / f^eq_q,
+// (the paper's closed form for omega_b = omega), omega_h = 1 if dh = 0.
+// The parts of the non-equilibrium n = f - f^eq are obtained in population
+// space without a moment basis: the second-order part is the Hermite
+// projection w_q H2(c_q):Pi / (2 c_s^4), H2 = c c - c_s^2 I, Pi = sum c c n
+// (the weighted basis spans the same order-2 space on all three stencils);
+// its bulk part is w_q (|c|^2 - D c_s^2) tr Pi / (2 D c_s^4); the first-order
+// part (Guo's half-force shift) is w_q c_q . J / c_s^2, J = sum c n; the rest
+// of n is dh.  The Guo source has components of orders 1 and 2 only and
+// enters as in the MRT operator, (1 - omega/2) on its shear and
+// (1 - omega_b/2) on its bulk part.
+// Reciprocal for the entropic weights 1/f^eq: the hardware approximation
+// refined by Newton steps r <- r (2 - x r) (one in FP32, two in FP64).
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+}
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  return r * (2.0 - x * r);
+}
+
+template <class L, class R>
+__device__ __forceinline__ void collide_kbc(R* f, const R* F, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr R cs2 = R(1.0 / 3.0);
+  R drho, jx, jy, jz;
+  density_momentum<L>(f, drho, jx, jy, jz);
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (jx + R(0.5) * F[0]) * inv, uy = (jy + R(0.5) * F[1]) * inv,
+          uz = (jz + R(0.5) * F[2]) * inv;
+  const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+  // pass 1: non-equilibrium n = f - f^eq (f^eq = f - n later) and its moments
+  R n[L::Q];
+  R Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0, Jx = 0, Jy = 0, Jz = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R w = R(weight<L>(q));
+    const R cu = cdot<L>(q, ux, uy, uz);
+    n[q] = f[q] - w * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));   // f^eq shifted by w rho_0
+    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    if (cx != 0) Pxx += n[q];
+    if (cy != 0) Pyy += n[q];
+    if (cz != 0) Pzz += n[q];
+    if (cx * cy == 1) Pxy += n[q];
+    if (cx * cy == -1) Pxy -= n[q];
+    if (cx * cz == 1) Pxz += n[q];
+    if (cx * cz == -1) Pxz -= n[q];
+    if (cy * cz == 1) Pyz += n[q];
+    if (cy * cz == -1) Pyz -= n[q];
+    if (cx == 1) Jx += n[q];
+    if (cx == -1) Jx -= n[q];
+    if (cy == 1) Jy += n[q];
+    if (cy == -1) Jy -= n[q];
+    if (cz == 1) Jz += n[q];
+    if (cz == -1) Jz -= n[q];
+  }
+  const R tr = Pxx + Pyy + Pzz;
+  const R trD = tr * (R(1) / R(D));
+  // second-order part of n at q (Hermite projection), and its bulk part
+  auto d2_of = [&](int q) {
+    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    R h2 = -cs2 * tr;
+    if (cx != 0) h2 += Pxx;
+    if (cy != 0) h2 += Pyy;
+    if (cz != 0) h2 += Pzz;
+    if (cx * cy != 0) h2 += R(2 * cx * cy) * Pxy;
+    if (cx * cz != 0) h2 += R(2 * cx * cz) * Pxz;
+    if (cy * cz != 0) h2 += R(2 * cy * cz) * Pyz;
+    return R(4.5 * weight<L>(q)) * h2;
+  };
+  auto db_of = [&](int q) {
+    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    return R(4.5 * weight<L>(q) * ((double)(cx * cx + cy * cy + cz * cz) - D / 3.0)) * trD;
+  };
+  // pass 2: dh (kept in n) and the entropic products
+  R sh = 0, bh = 0, hh = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R d2 = d2_of(q), db = db_of(q);
+    const R dh = n[q] - R(3 * weight<L>(q)) * cdot<L>(q, Jx, Jy, Jz) - d2;
+    const R ie = recip(R(weight<L>(q)) * p.rho0 + (f[q] - n[q]));
+    const R dhe = dh * ie;
+    sh += (d2 - db) * dhe;
+    bh += db * dhe;
+    hh += dh * dhe;
+    n[q] = dh;
+  }
+  const R om = p.om, omb = p.om_b;
+  const R omh = hh > R(0) ? R(1) + ((R(1) - om) * sh + (R(1) - omb) * bh) / hh : R(1);
+  const R fs = R(1) - R(0.5) * om, fbs = (R(1) - R(0.5) * omb) - fs;
+  const R dom = om - omb;
+  const R uFD = R(2) * uF * (R(1) / R(D));   // trace of the source's second moment u F + F u, over D
+  // pass 3: relax; the Guo source's order-1 part enters fully, its order-2
+  // part with (1 - omega/2) (shear) and (1 - omega_b/2) (bulk)
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const R w = R(weight<L>(q));
+    const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    const R cu = cdot<L>(q, ux, uy, uz);
+    const R cF = cdot<L>(q, F[0], F[1], F[2]);
+    const R s2 = w * (R(9) * cu * cF - R(3) * uF);
+    const R s2b = R(4.5 * weight<L>(q) * ((double)(cx * cx + cy * cy + cz * cz) - D / 3.0)) * uFD;
+    f[q] = f[q] - om * d2_of(q) + dom * db_of(q) - omh * n[q] + R(3) * w * cF + fs * s2 + fbs * s2b;
+  }
+}
+
 template <class L, int M, class R>
 __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>& p) {
   if constexpr (M == M_SRT) collide_srt<L>(f, F, p);
@@ -938,6 +1056,7 @@ __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>
   else if constexpr (M == M_MRT_SMAG && L::Q == 19) collide_mrt_gs<L, R, true>(f, F, p);
   else if constexpr (M == M_MRT_SMAG) collide_mrt<L, R, true>(f, F, p);
   else if constexpr (M == M_CUMULANT_GEN) collide_cumulant_general<L>(f, F, p);
+  else if constexpr (M == M_KBC) collide_kbc<L>(f, F, p);
   else collide_cumulant<L>(f, F, p);
 }
 

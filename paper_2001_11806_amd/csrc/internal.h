@@ -36,7 +36,7 @@ inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
 hipError_t launch_sweep(int stencil, int method, int dtype, int phase, const void* src, void* dst,
                         const uint8_t* flags, const void* force_y, const Geo& g, const Params& p,
                         int has_mask, hipStream_t s);
-bool sweep_supported(int stencil, int method);
+bool sweep_supported(int stencil, int method);   // method: kernel code (collide.h)
 
 // auxiliary (aux.hip)
 // flags (one byte per cell) and the bounced-link bits of every cell

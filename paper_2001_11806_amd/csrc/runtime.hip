@@ -91,10 +91,23 @@ void free_ctx(lbm_ctx* c) {
   delete c;
 }
 
+// Kernel method code (collide.h): the ABI method, its Smagorinsky variant,
+// the general-rate cumulant kernel, or KBC.
+int kernel_method(const lbm_config* cfg) {
+  if (cfg->rates.cs_smag > 0) return cfg->method == LBM_SRT ? 4 : 5;
+  if (cfg->method == LBM_KBC) return 7;
+  if (cfg->method == LBM_CUMULANT) {   // unit higher-order rates: the Gaussian-reconstruction kernel
+    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
+    for (int i = 0; i < nhi; ++i)
+      if (cfg->rates.omega_hi[i] != 1.0) return 6;
+  }
+  return cfg->method;
+}
+
 int32_t validate(const lbm_config* cfg) {
   if (!cfg) return fail(LBM_EINVAL, "cfg is NULL");
   if (cfg->stencil < 0 || cfg->stencil > 2) return fail(LBM_EINVAL, "unknown stencil %d", cfg->stencil);
-  if (cfg->method < 0 || cfg->method > 3) return fail(LBM_EINVAL, "unknown method %d", cfg->method);
+  if (cfg->method < 0 || cfg->method > 4) return fail(LBM_EINVAL, "unknown method %d", cfg->method);
   if (cfg->dtype < 0 || cfg->dtype > 3) return fail(LBM_EINVAL, "unknown dtype %d", cfg->dtype);
   if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
     return fail(LBM_EINVAL, "lattice dims must be >= 1 (got %d x %d x %d)", cfg->nx, cfg->ny, cfg->nz);
@@ -114,6 +127,8 @@ int32_t validate(const lbm_config* cfg) {
       return fail(LBM_EINVAL, "omega_odd = %g is outside (0, 2)", r.omega_odd);
     }
   }
+  if (cfg->method == LBM_KBC && !rate_ok(r.omega_bulk))
+    return fail(LBM_EINVAL, "omega_bulk = %g is outside (0, 2)", r.omega_bulk);
   if (cfg->method == LBM_MRT || cfg->method == LBM_CUMULANT) {
     if (!rate_ok(r.omega_bulk)) return fail(LBM_EINVAL, "omega_bulk = %g is outside (0, 2)", r.omega_bulk);
     const int nhi = cfg->stencil == LBM_D3Q27 ? 4 : 2;   // highest moment order 2 DIM, or 4 on D3Q19
@@ -126,7 +141,7 @@ int32_t validate(const lbm_config* cfg) {
   if (r.cs_smag > 0 && cfg->checkpoint_every > 0)
     return fail(LBM_EUNSUPPORTED, "the adjoint of the Smagorinsky model is not implemented");
   if (cfg->pattern != 0 && cfg->pattern != 1) return fail(LBM_EINVAL, "pattern must be 0 (two arrays) or 1 (AA)");
-  if (!sweep_supported(cfg->stencil, cfg->method))
+  if (!sweep_supported(cfg->stencil, kernel_method(cfg)))
     return fail(LBM_EUNSUPPORTED, "method %d is not implemented on stencil %d", cfg->method, cfg->stencil);
   if (cfg->method == LBM_CUMULANT && !cfg->compressible)
     return fail(LBM_EUNSUPPORTED, "the cumulant operator is compressible only");
@@ -293,12 +308,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   lbm_ctx* c = new lbm_ctx();
   c->cfg = *cfg;
   c->Q = q_of(cfg->stencil);
-  c->kmethod = cfg->rates.cs_smag > 0 ? (cfg->method == LBM_SRT ? 4 : 5) : cfg->method;
-  if (cfg->method == LBM_CUMULANT) {   // unit higher-order rates: the Gaussian-reconstruction kernel
-    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
-    for (int i = 0; i < nhi; ++i)
-      if (cfg->rates.omega_hi[i] != 1.0) c->kmethod = 6;
-  }
+  c->kmethod = kernel_method(cfg);
   c->g = make_geo(*cfg);
   c->p = make_params(*cfg);
   c->p.moving = moving;

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("LBM_MI355X_LIB", os.path.join(_HERE, "liblbm_mi355x.s
 
 STENCILS = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 QS = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
-METHODS = {"SRT": 0, "TRT": 1, "MRT": 2, "CUMULANT": 3}
+METHODS = {"SRT": 0, "TRT": 1, "MRT": 2, "CUMULANT": 3, "KBC": 4}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 

@@ -77,6 +77,9 @@ def _create(lib, **kw):
     (dict(method="CUMULANT"), B.EUNSUPPORTED, "not implemented"),
     (dict(method="CUMULANT", stencil="D3Q27", omega_hi=(1, 2.2, 1, 1)), B.EINVAL, "omega_hi[1]"),
     (dict(method="CUMULANT", stencil="D3Q27", compressible=False), B.EUNSUPPORTED, "compressible"),
+    (dict(method="KBC", omega_bulk=2.5), B.EINVAL, "omega_bulk"),
+    (dict(method="KBC", cs_smag=0.1), B.EUNSUPPORTED, "Smagorinsky"),
+    (dict(method="KBC", checkpoint_every=2, max_tape_steps=4), B.EUNSUPPORTED, "adjoint"),
     (dict(pattern=2), B.EINVAL, "pattern"),
     (dict(pattern=1, method="TRT", magic=3 / 16, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
     (dict(launch_mode=3), B.EINVAL, "launch_mode"),

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 
 COMBOS = [("D2Q9", "SRT"), ("D2Q9", "TRT"), ("D2Q9", "MRT"), ("D2Q9", "CUMULANT"),
           ("D3Q19", "SRT"), ("D3Q19", "TRT"), ("D3Q19", "MRT"),
-          ("D3Q27", "SRT"), ("D3Q27", "TRT"), ("D3Q27", "MRT"), ("D3Q27", "CUMULANT")]
+          ("D3Q27", "SRT"), ("D3Q27", "TRT"), ("D3Q27", "MRT"), ("D3Q27", "CUMULANT"),
+          ("D2Q9", "KBC"), ("D3Q19", "KBC"), ("D3Q27", "KBC")]
 DTYPES = ["f64", "f32", "bf16", "f16"]
 MRT_RATES = dict(RATES, omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.1, 0.9, 1.3, 1.05))
 CUM_RATES = dict(RATES, omega=1 / 0.55, omega_bulk=1.1, omega_hi=(1.0, 1.0, 1.0, 1.0))
@@ -31,7 +32,7 @@ BOUND_U = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-2, "f16": 3e-3}
 
 
 def _rates(method):
-    return MRT_RATES if method == "MRT" else (CUM_RATES if method == "CUMULANT" else RATES)
+    return MRT_RATES if method in ("MRT", "KBC") else (CUM_RATES if method == "CUMULANT" else RATES)
 
 
 def _setup(stencil, method, dtype, seed=1):
