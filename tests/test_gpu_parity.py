@@ -313,6 +313,29 @@ def test_moving_walls_parity(stencil, method, dtype, pattern):
 
 
 @pytest.mark.parametrize("pattern", [0, 1])
+def test_lid_driven_cavity_on_gpu(pattern):
+    """Creeping lid-driven cavity (D2Q9 SRT, lid = moving-wall type 2):
+    6000 steps on the GPU against the oracle, and the Stokes mirror symmetry
+    of the steady field.  Bound: the oracle holds unshifted populations
+    (|f| ~ 0.44) while |u| ~ 1e-4, so each of its FP64 operations perturbs u
+    by ~ 1.1e-16 * 0.44 / 1e-4 ~ 5e-13 relative; the steady state sums a few
+    hundred such contributions, hence 1e-10 (measured 5.8e-12)."""
+    need_gpu()
+    from tests.test_oracle_physics import _asymmetry, lid_driven_cavity
+    N, U = 24, 1e-4
+    u_ref, mask, table = lid_driven_cavity(N, U, 6000)
+    g = make_gpu("D2Q9", "SRT", "f64", (N, N, 1), mask, dict(RATES, omega=1.0), pattern=pattern)
+    g.set_wall_velocity(2, table[2])
+    g.init_equilibrium()
+    g.step(6000)
+    _, uu = g.macroscopic()
+    g.close()
+    u = to_np(uu)[:2, 0]
+    assert rel_l2(u, u_ref) <= 1e-10
+    assert _asymmetry(u) < 2e-4
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
 def test_couette_exact_on_gpu(pattern):
     """Moving top wall over a resting wall: exact linear profile (FP64)."""
     need_gpu()

@@ -190,3 +190,42 @@ def test_couette_moving_wall_exact(method):
     np.testing.assert_allclose(u[0, 0, 1:H + 1, 0], U * (y - 0.5) / H, rtol=1e-9, atol=1e-14)
     # the moving wall drags: momentum enters through it
     assert run.conserved(cfg, P, mask)[1] > 0
+
+
+def lid_driven_cavity(N, U, steps, tau=1.0):
+    """D2Q9 SRT cavity: resting walls at x = 0, x = N-1, y = 0; the top row
+    y = N-1 is a lid (wall type 2) moving with U along x."""
+    cfg = run.Config("D2Q9", "SRT", dict(omega=1 / tau))
+    mask = np.zeros((1, N, N), dtype=np.uint8)
+    mask[0, 0, :] = 1
+    mask[0, :, 0] = 1
+    mask[0, :, N - 1] = 1
+    mask[0, N - 1, :] = 2
+    table = np.zeros((3, 3))
+    table[2] = (U, 0.0, 0.0)
+    P = run.init_equilibrium(cfg, np.ones((1, N, N)), np.zeros((3, 1, N, N)), mask)
+    P = run.run(cfg, P, steps, mask, None, table)
+    _, u = run.readout(cfg, P, mask)
+    return u[:2, 0], mask, table
+
+
+def _asymmetry(u):
+    """Departure from the Stokes-flow symmetry u_x(x, y) = u_x(L - x, y),
+    u_y(x, y) = -u_y(L - x, y), relative to max |u|."""
+    ux, uy = u
+    return max(np.max(np.abs(ux - ux[:, ::-1])), np.max(np.abs(uy + uy[:, ::-1]))) / np.max(np.abs(u))
+
+
+def test_lid_driven_cavity_stokes_symmetry():
+    """Creeping lid-driven cavity.  Stokes flow is linear and reversible, so
+    reflecting x and reversing the flow maps the solution to itself: the
+    steady field is mirror-symmetric about the vertical centre line.  At
+    Re = 0.002 the departure is the O(Re) inertia; at Re = 2 it is a hundred
+    times larger (negative control).  The lid drags the fluid along below it
+    and the return flow runs the other way near the bottom."""
+    u_slow = lid_driven_cavity(24, 1e-4, 6000)[0]
+    u_fast = lid_driven_cavity(24, 1e-2, 6000)[0]
+    a_slow, a_fast = _asymmetry(u_slow), _asymmetry(u_fast)
+    assert a_slow < 2e-4, a_slow
+    assert a_fast > 50 * a_slow, (a_slow, a_fast)
+    assert u_slow[0][-2, 12] > 0 > u_slow[0][1, 12]
