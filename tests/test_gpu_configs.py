@@ -316,3 +316,52 @@ def test_c5_kolmogorov_laminar_slice():
         dev = np.max(np.abs(ux - ref)) / np.max(np.abs(ref))
         print("Kolmogorov %s: max rel deviation %.2e" % (dtype, dev))
         assert dev < tol
+
+
+# ------------------------------------------------------------------ size limit
+def test_largest_lattice_at_the_32bit_cell_index_limit():
+    """The cell index is 32-bit: N < 2^31.  A 46340 x 46340 D2Q9 lattice has
+    N = 2^31 - 88 048 cells; with FP32 storage the two PDF grids take 155 GB.
+    One SRT step from a closed-form velocity field, checked against the
+    oracle at sampled cells over the whole index range (the last rows and
+    both ends of every periodic wrap included)."""
+    need_gpu()
+    n = 46340
+    dims = (n, n, 1)
+    assert n * n < 2 ** 31
+    free, _ = torch.cuda.mem_get_info()
+    if free < 240e9:
+        pytest.skip("needs 240 GB of free device memory")
+    cells = np.concatenate([inputs.sample_cells(dims, 3000, 13),
+                            np.arange(n * n - 3 * n, n * n, 997), np.arange(n * n - 40, n * n)])
+    cells = np.unique(cells)
+    print("case D2Q9 SRT f32", dims, "sample", cells.size, flush=True)
+    g = make_gpu("D2Q9", "SRT", "f32", dims, None, SRT)
+    k = 2 * np.pi / n
+    ax = torch.arange(n, device="cuda", dtype=torch.float64)
+    u = torch.zeros((3, 1, n, n), device="cuda", dtype=torch.float32)
+    u[0, 0] = (0.02 * torch.sin(3 * k * ax)[None, :] * torch.cos(k * ax)[:, None]).float()
+    u[1, 0] = (-0.01 * torch.cos(2 * k * ax)[None, :] * torch.sin(5 * k * ax)[:, None]).float()
+    g.init_equilibrium(None, u)
+    uflat = u.reshape(3, -1)
+    cfg = orun.Config("D2Q9", "SRT", SRT, storage="f32")
+
+    def P_of(q, idx):
+        uu = to_np(uflat[:, torch.as_tensor(idx, device="cuda")]).astype(np.float64)
+        return orun.quantize(cfg, oeq.equilibrium(cfg.lat, np.ones(idx.size), uu))[q]
+
+    post = orun.step_at_cells(cfg, P_of, cells, dims)
+    rho_o, u_o = orun.readout(cfg, post)
+    del u, uflat
+    torch.cuda.empty_cache()
+    g.step(1)
+    rho_g, u_g = g.macroscopic(dtype=torch.float32)
+    g.close()
+    idx = torch.as_tensor(cells, device=rho_g.device)
+    rg = to_np(rho_g.reshape(-1)[idx]).astype(np.float64)
+    ug = to_np(u_g.reshape(3, -1)[:, idx]).astype(np.float64)
+    del rho_g, u_g
+    torch.cuda.empty_cache()
+    # FP32 storage and readout: a few ulp of values of size 1 (rho) and 0.02 (u)
+    assert np.max(np.abs(rg - rho_o)) <= 1e-6
+    assert np.max(np.abs(ug[:2] - u_o[:2])) <= 2e-8 + 1e-6 * np.max(np.abs(u_o))
