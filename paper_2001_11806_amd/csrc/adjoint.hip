@@ -76,7 +76,8 @@ __device__ __forceinline__ size_t post_slot(int layout, int q, const CellIdx& c,
   if (layout == 1) return (size_t)opp<L>(q) * N + c.cell;
   LBM_NEIGHBOURS(c, g)
   const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-  const bool bounced = q > 0 && has_mask && (flags[d] & 1);
+  // a neighbour can be solid only where the cell's own flag says so
+  const bool bounced = q > 0 && has_mask && (flags[c.cell] & 2) && (flags[d] & 1);
   return bounced ? (size_t)opp<L>(q) * N + c.cell : (size_t)q * N + d;
 }
 

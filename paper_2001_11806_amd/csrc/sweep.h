@@ -300,8 +300,8 @@ __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int 
                                           const CellIdx& c, const Geo& g, double* v,
                                           const typename Storage<T>::R* wall, double rho0) {
   const size_t N = (size_t)g.N;
-  const bool solid = has_mask && (flags[c.cell] & 1);
-  if (layout == 0 || solid) {
+  const int fl = has_mask ? flags[c.cell] : 0;
+  if (layout == 0 || (fl & 1)) {
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P + q * N + c.cell);
   } else if (layout == 1) {
@@ -312,7 +312,7 @@ __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int 
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      const int fs = (q > 0 && (fl & 2)) ? flags[d] : 0;   // neighbours are read next to walls only
       v[q] = (double)Storage<T>::load((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d);
       if (fs & 1) v[q] -= (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0);
     }
@@ -324,8 +324,8 @@ __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_m
                                            const Geo& g, const double* v, const typename Storage<T>::R* wall,
                                            double rho0) {
   const size_t N = (size_t)g.N;
-  const bool solid = has_mask && (flags[c.cell] & 1);
-  if (layout == 0 || solid) {
+  const int fl = has_mask ? flags[c.cell] : 0;
+  if (layout == 0 || (fl & 1)) {
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) store_from_double(P + q * N + c.cell, v[q]);
   } else if (layout == 1) {
@@ -336,7 +336,7 @@ __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_m
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
-      const int fs = (q > 0 && has_mask) ? flags[d] : 0;
+      const int fs = (q > 0 && (fl & 2)) ? flags[d] : 0;   // neighbours are read next to walls only
       if (fs & 1)
         store_from_double(P + opp<L>(q) * N + c.cell,
                           v[q] + (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0));
