@@ -329,6 +329,7 @@ def test_largest_lattice_at_the_32bit_cell_index_limit():
     n = 46340
     dims = (n, n, 1)
     assert n * n < 2 ** 31
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     if free < 240e9:
         pytest.skip("needs 240 GB of free device memory")

@@ -173,6 +173,31 @@ def test_solid_cells_untouched_any_step_count(steps):
         assert np.all(P[q][s] == w[q])
 
 
+@pytest.mark.parametrize("dtype,bad", [("f64", float("nan")), ("f32", float("inf")), ("f16", 1e6)])
+def test_nonfinite_totals_are_reported(dtype, bad):
+    """The FP64 totals flag NaN or Inf (lbm_conserved returns LBM_ENONFINITE):
+    a NaN or Inf written into one population, or a value beyond the FP16
+    range that the shifted storage rounds to Inf; it is still flagged after
+    it has spread for a few steps."""
+    need_gpu()
+    from paper_2001_11806_amd.lbm import LBMError
+    dims = (70, 6, 4)
+    g = make_gpu("D3Q19", "SRT", dtype, dims, None, RATES)
+    g.init_equilibrium()
+    g.conserved()
+    P = g.get_pdfs()
+    P[5, 2, 3, 40] = bad
+    g.set_pdfs(P)
+    with pytest.raises(LBMError, match="not finite"):
+        g.conserved()
+    g.step(3)
+    with pytest.raises(LBMError, match="not finite"):
+        g.conserved()
+    g.init_equilibrium()
+    g.conserved()   # a fresh state is finite again
+    g.close()
+
+
 def test_zero_steps_and_set_pdfs_roundtrip():
     need_gpu()
     dims = (70, 6, 4)
