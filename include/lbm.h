@@ -7,14 +7,17 @@
  *   - lattice: DdQq velocity sets on a regular periodic grid (Sec. III-A);
  *   - one time step = pull streaming from the upstream neighbours followed by
  *     the local collision, fused in one kernel over two arrays
- *     (Sec. IV-B, Fig. "stream-pull-collide");
+ *     (Sec. IV-B, Fig. "stream-pull-collide"), or in place in one array with
+ *     the AA pattern (Sec. IV-B, Fig. "AA update pattern");
  *   - collision: SRT (Eq. 1), TRT (Sec. III-C), MRT in a lattice-weighted
  *     orthogonal moment basis (Eq. 4, Sec. III-C "MRT"), cumulant (Eq. 9,
- *     Sec. III-B); equilibrium Eq. (3) at second order, density and velocity
+ *     Sec. III-B), the Smagorinsky model (Sec. III-C "Turbulence models",
+ *     Eqs. 11-14) and the entropic KBC model (Sec. III-C "Entropic KBC
+ *     Models"); equilibrium Eq. (3) at second order, density and velocity
  *     from Eq. (2); body force by Guo's scheme (cited in Sec. I);
- *   - walls: halfway bounce-back of the resting-wall case of the velocity
- *     bounce-back rule (Sec. III-C "Boundary Conditions"), compiled into the
- *     sweep from a solid mask (Sec. IV-B "Boundary Conditions").
+ *   - walls: halfway velocity bounce-back (Sec. III-C "Boundary Conditions")
+ *     for resting and moving walls, compiled into the sweep from a solid mask
+ *     (Sec. IV-B "Boundary Conditions").
  * Extensions not in the paper: PDFs stored shifted by w_q rho_0 in FP32, BF16
  * or FP16 with FP32 collision arithmetic; a discrete adjoint sweep with a
  * checkpoint tape.
@@ -150,10 +153,11 @@ int32_t lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u);
 int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
                              int32_t field_dtype);
 
-/* Advance n >= 0 time steps (one fused stream-pull-collide launch each;
- * with launch_mode 0 small lattices replay a captured graph of 32 launches).
- * With the tape enabled, the state at every multiple of k steps below
- * max_tape_steps is copied into the tape first. */
+/* Advance n >= 0 time steps (one fused stream-pull-collide launch each, the
+ * AA even and odd kernels alternating with pattern 1; with launch_mode 0
+ * small lattices replay a captured graph of 32 launches).  With the tape
+ * enabled, the state at every multiple of k steps below max_tape_steps is
+ * copied into the tape first (in the two-array layout). */
 int32_t lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Readout of the stored (post-collision) state: rho = sum f,

@@ -1,12 +1,13 @@
-// The fused stream-pull-collide sweep (two-array pattern).
+// The fused stream-pull-collide sweep: two-array pattern, the AA pattern,
+// and the stored-layout helpers.
 //
 // Paper, Sec. IV-B and Fig. "stream-pull-collide": every cell pulls
 // population q from its upstream neighbour x - c_q in the source array,
 // collides locally and writes all Q results to its own slot in the
-// destination array.  Halfway bounce-back for resting walls (Sec. III-C
-// "Boundary Conditions", wall velocity 0) is compiled into the gather
-// (Sec. IV-B "Boundary Conditions", flag field variant): if x - c_q is solid
-// the cell reads its own outgoing population opp(q) instead.
+// destination array.  Halfway velocity bounce-back (Sec. III-C "Boundary
+// Conditions") is compiled into the gather (Sec. IV-B "Boundary Conditions",
+// flag field variant): if x - c_q is solid the cell reads its own outgoing
+// population opp(q) instead, plus the moving-wall term.
 //
 // MI355X mapping
 //   - structure-of-arrays layout P[q][z][y][x]; a wavefront reads 64
