@@ -106,8 +106,8 @@ def run_forward(torch, LBM, inputs, stencil, method, dtype, dims, rates, mask, u
     res["hbm_frac"] = res["achieved_GBps"] * 1e9 / PEAK_HBM
     cons = lbm.conserved()
     res["mass"] = float(cons[0])
-    _, uu = lbm.macroscopic(dtype=torch.float32)
-    res["u_out"] = uu
+    rr, uu = lbm.macroscopic(dtype=torch.float64)
+    res["u_out"], res["rho_out"] = uu, rr
     lbm.close()
     return res
 
@@ -144,6 +144,7 @@ def main():
     head = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f64", (n, n, n), trt, mask, u, F=F,
                        steps=args.steps, warmup=args.warmup)
     u64 = head.pop("u_out")
+    head.pop("rho_out")
     log("  %.0f MLUPS, %.0f GB/s" % (head["mlups"], head["achieved_GBps"]))
     extras = {}
     only = set(filter(None, args.only.split(",")))
@@ -154,6 +155,7 @@ def main():
         r32 = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f32", (n, n, n), trt, mask, u, F=F,
                           steps=args.steps, warmup=args.warmup)
         u32 = r32.pop("u_out")
+        r32.pop("rho_out")
         fl = torch.from_numpy(mask == 0).to(dev)
         d = (u32.double() - u64.double())[:, fl]
         r32["rel_l2_u_vs_f64_same_gpu"] = float(d.norm() / u64.double()[:, fl].norm())
@@ -164,6 +166,7 @@ def main():
         raa = run_forward(torch, LBM, inputs, "D3Q19", "TRT", "f64", (n, n, n), trt, mask, u, F=F,
                           steps=args.steps, warmup=args.warmup, pattern=1)
         uaa = raa.pop("u_out")
+        raa.pop("rho_out")
         raa["u_equal_to_two_array_run"] = bool(torch.equal(uaa, u64))
         extras["c2_d3q19_trt_256_f64_aa"] = raa
         log("  %.0f MLUPS, %.0f GB/s, identical to two-array: %s" % (raa["mlups"], raa["achieved_GBps"],
@@ -189,22 +192,29 @@ def main():
         torch.cuda.empty_cache()
 
     if want("c3"):
+        # the full 500-step run in every storage type; FP64 on the same GPU
+        # (parity-checked against the oracle) is the reference for the errors
         n3 = 384
-        log("C3 D3Q27 cumulant 384^3: building solenoidal field")
+        log("C3 D3Q27 cumulant 384^3, 500 steps: building solenoidal field")
         modes = inputs.solenoidal_modes(seed=3)
         u3 = inputs.solenoidal_velocity(n3, modes, dtype=np.float32)
         cum = dict(omega=1 / 0.55, omega_bulk=1.0, omega_hi=(1.0,) * 4)
         ref = None
-        for dt in ("f32", "bf16", "f16"):
+        for dt in ("f64", "f32", "bf16", "f16"):
             r = run_forward(torch, LBM, inputs, "D3Q27", "CUMULANT", dt, (n3, n3, n3), cum, None, u3,
-                            steps=50, warmup=5)
-            uo = r.pop("u_out")
+                            steps=495, warmup=5)
+            uo, ro = r.pop("u_out"), r.pop("rho_out")
             if ref is None:
-                ref = uo
+                ref = (uo, ro)
             else:
-                r["rel_l2_u_vs_f32_same_gpu_50_steps"] = float((uo - ref).double().norm() / ref.double().norm())
+                r["rel_l2_u_vs_f64_500_steps"] = float((uo - ref[0]).norm() / ref[0].norm())
+                r["rel_l2_rho_minus_1_vs_f64_500_steps"] = float((ro - ref[1]).norm() / (ref[1] - 1).norm())
             extras["c3_d3q27_cumulant_384_%s" % dt] = r
-            log("  %s: %.0f MLUPS, %.0f GB/s" % (dt, r["mlups"], r["achieved_GBps"]))
+            log("  %s: %.0f MLUPS, %.0f GB/s%s" % (dt, r["mlups"], r["achieved_GBps"], "" if dt == "f64" else
+                ", rel L2 vs FP64: u %.2e, rho-1 %.2e" % (r["rel_l2_u_vs_f64_500_steps"],
+                                                          r["rel_l2_rho_minus_1_vs_f64_500_steps"])))
+            del uo, ro
+            torch.cuda.empty_cache()
         del ref, u3
         torch.cuda.empty_cache()
 
@@ -223,22 +233,23 @@ def main():
 
     if want("c5"):
         n5 = 512
-        log("C5 D3Q27 MRT 512^3: building noise field")
+        log("C5 D3Q27 MRT 512^3, 1000 steps: building noise field")
         u5 = inputs.uniform_noise_velocity((n5, n5, n5), 1e-3, 5, None, dtype=np.float32)
         prof = inputs.kolmogorov_force_profile(n5, 1e-6)
         mrt = dict(omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.0,) * 4)
         ref = None
         for dt in ("f64", "f16"):
             r = run_forward(torch, LBM, inputs, "D3Q27", "MRT", dt, (n5, n5, n5), mrt, None, u5, profile=prof,
-                            steps=20, warmup=3)
-            uo = r.pop("u_out")
+                            steps=995, warmup=5)
+            uo, ro = r.pop("u_out"), r.pop("rho_out")
             if ref is None:
                 ref = uo
             else:
-                r["rel_l2_u_vs_f64_same_gpu_23_steps"] = float((uo - ref).double().norm() / ref.double().norm())
+                r["rel_l2_u_vs_f64_same_gpu_1000_steps"] = float((uo - ref).norm() / ref.norm())
             extras["c5_d3q27_mrt_512_%s" % dt] = r
-            log("  %s: %.0f MLUPS, %.0f GB/s" % (dt, r["mlups"], r["achieved_GBps"]))
-            del uo
+            log("  %s: %.0f MLUPS, %.0f GB/s%s" % (dt, r["mlups"], r["achieved_GBps"], "" if dt == "f64" else
+                ", rel L2 u vs FP64 after 1000 steps %.2e" % r["rel_l2_u_vs_f64_same_gpu_1000_steps"]))
+            del uo, ro
             torch.cuda.empty_cache()
         del ref, u5
 

@@ -11,6 +11,8 @@ x fastest in memory; masks are uint8 with 1 = solid; force profiles are
 and a channel, Sec. V); there is no dataset.
 """
 
+import functools
+
 import numpy as np
 
 
@@ -82,11 +84,14 @@ def sphere_channel_mask(n=128, seed=4, radius=8.0, fraction=0.05, nx=None, nz=No
     return mask
 
 
-def solenoidal_modes(seed=3, nmodes=32, kmax=4, umax=0.05):
+@functools.lru_cache(maxsize=None)
+def solenoidal_modes(seed=3, nmodes=32, kmax=4, umax=0.05, n_norm=384):
     """Random Fourier modes for a divergence-free field:
     u(x) = sum_m a_m cos(2 pi k_m . x / n + phi_m), integer k_m in
-    [-kmax, kmax]^3 without 0, a_m perpendicular to k_m, scaled so that
-    sum_m |a_m| = umax (hence |u| <= umax everywhere)."""
+    [-kmax, kmax]^3 without 0, a_m perpendicular to k_m, scaled so that the
+    largest speed |u| on the n_norm^3 lattice is umax (smaller lattices
+    sample the same field more coarsely, so their largest speed is at most
+    umax)."""
     rng = np.random.default_rng(seed)
     ks, amps, phis = [], [], []
     while len(ks) < nmodes:
@@ -100,8 +105,12 @@ def solenoidal_modes(seed=3, nmodes=32, kmax=4, umax=0.05):
         amps.append(a)
         phis.append(rng.uniform(0, 2 * np.pi))
     amps = np.array(amps)
-    amps *= umax / np.linalg.norm(amps, axis=1).sum()
-    return np.array(ks), amps, np.array(phis)
+    amps /= np.linalg.norm(amps, axis=1).sum()
+    modes = (np.array(ks), amps, np.array(phis))
+    u = solenoidal_velocity(n_norm, modes)
+    speed = np.sqrt((u * u).sum(axis=0)).max()
+    del u
+    return modes[0], amps * (umax / speed), modes[2]
 
 
 def solenoidal_velocity(n, modes, dtype=np.float64):
