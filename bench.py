@@ -279,7 +279,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": head["hbm_frac"], "traffic": traffic,
                      "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
-                     "kernel": "k_sweep<D3Q19, TRT, double>"},
+                     "kernel": "k_sweep<D3Q19, TRT, double>",
+                     # attainable line: the 19-plane FP64 copy of the same size, same run
+                     "copy_line_GBps": extras.get("copy_q19_f64_256", {}).get("GBps"),
+                     "frac_of_copy_line": (head["achieved_GBps"] / extras["copy_q19_f64_256"]["GBps"]
+                                           if "copy_q19_f64_256" in extras else None)},
         "cpu_baseline": cpu,
         "extras": extras,
         "wall_s": round(time.time() - t_start, 1),
