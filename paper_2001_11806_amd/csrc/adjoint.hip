@@ -10,23 +10,23 @@
 //            t_q = lambda_q w_q (3 omega rho (1 + 3 c.u) + 9 (1 - omega/2) c.F),
 //            s0 = sum_q lambda_q w_q
 //   h_p    = (1 - omega) lambda_p + alpha + (c_p - u).beta / rho
-// and h_p goes back along the link it was pulled through: to slot
-// (x - c_p, p), or to (x, opp(p)) if that link was bounced.  Each slot of
-// lambda^t receives exactly one value (the gather is a permutation of fluid
-// links), so the scatter has no write conflicts.
+// and h_p goes back along the link it was pulled through: to the entry
+// lambda^t(x - c_p, p), or lambda^t(x, opp(p)) if that link was bounced.
 // dL/dF collects, per cell,
 //   sum_q lambda_q dS_q/dF_b + beta_b / (2 rho)
 //   = (1 - omega/2) [sum_q c_qb lambda_q w_q (3 + 9 c.u) - 3 u_b s0] + beta_b / (2 rho),
 // reduced per block in FP64.
 //
-// AA pattern (one array, Sec. IV-B): lambda lives in one array too, placed
-// like the stored state of the same time.  Each forward AA kernel reads and
-// writes the same set of slots per cell, so its transpose does as well: the
-// adjoint of the even kernel reads lambda from the cell's own slots opp(q)
-// and writes h to its own slots q; the adjoint of the odd kernel reads
-// lambda from the slots the forward kernel pushed to, (x + c_q, q) or
-// (x, opp q) at a wall, and writes h to the slots it pulled from,
-// (x - c_q, opp q) or (x, q) at a wall.  Both run in place without races.
+// Storage of lambda: one array, laid out like the state of an AA run
+// (Sec. IV-B) at the same time, whichever pattern the forward run used (the
+// forward states come from the tape in the two-array layout either way).
+// Each AA kernel reads and writes the same set of slots per cell, so its
+// transpose does as well: the adjoint of the even kernel reads lambda from
+// the cell's own slots opp(q) and writes h to its own slots q; the adjoint
+// of the odd kernel reads lambda from the slots the forward kernel pushed
+// to, (x + c_q, q) or (x, opp q) at a wall, and writes h to the slots it
+// pulled from, (x - c_q, opp q) or (x, q) at a wall.  Both run in place
+// without races, and lambda needs one array instead of two.
 #include "sweep.h"
 
 namespace lbm {
@@ -89,7 +89,7 @@ __device__ __forceinline__ size_t post_slot(int layout, int q, const CellIdx& c,
 // values land on the fluid slots one to one in every layout.
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                  int has_mask, int layout,
+                                                  int has_mask, int layout, int lam_layout,
                                                   const typename Storage<T>::R* __restrict__ force_y,
                                                   const void* dL_drho, const void* dL_du, int fdt,
                                                   typename Storage<T>::R* __restrict__ lam,
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
       const R base = gr - (gx * ux + gy * uy + gz * uz) * inv;
 #pragma unroll
       for (int q = 0; q < L::Q; ++q)
-        lam[post_slot<L>(layout, q, c, g, flags, has_mask)] = base + cdot<L>(q, gx, gy, gz) * inv;
+        lam[post_slot<L>(lam_layout, q, c, g, flags, has_mask)] = base + cdot<L>(q, gx, gy, gz) * inv;
       dF[0] = -(double)gx / (2.0 * (double)rho);
       dF[1] = -(double)gy / (2.0 * (double)rho);
       dF[2] = -(double)gz / (2.0 * (double)rho);
@@ -183,54 +183,6 @@ __device__ __forceinline__ void adj_cell(const R* f, R* lam, R F0, R F1, R F2, c
   dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
   dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
   dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
-}
-
-// Two lambda arrays.  Each block adds its dL/dF contribution to its own FP64
-// accumulator slot (only that block's thread 0 touches the slot, launches
-// are stream-ordered), so the sum is deterministic and needs no reduction
-// launch per step.
-template <class L, class T>
-__global__ __launch_bounds__(512) void k_adj_sweep(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                   int has_mask, const typename Storage<T>::R* __restrict__ force_y,
-                                                   const typename Storage<T>::R* __restrict__ lam_in,
-                                                   typename Storage<T>::R* __restrict__ lam_out,
-                                                   double* __restrict__ partials, Geo g,
-                                                   CollideParams<typename Storage<T>::R> p) {
-  using R = typename Storage<T>::R;
-  const CellIdx c = cell_of(g);
-  const size_t N = (size_t)g.N;
-  double dF[3] = {0, 0, 0};
-  int fl = 0;
-  if (c.valid && has_mask) fl = flags[c.cell];
-  if (c.valid && !(fl & 1)) {
-    R f[L::Q];
-    uint32_t bb = 0;
-    gather<L, T>(P, flags, fl, c, g, f, &bb, p);
-    R lam[L::Q];
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) lam[q] = lam_in[q * N + c.cell];
-    adj_cell<L, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
-    // h goes back along the link it was pulled through: the upstream slot
-    // (x - c_q, q), addressed like the gather; a bounced link's upstream slot
-    // belongs to a solid cell (written at most once, never read) and its
-    // value goes to (x, opp(q)) instead.
-    LBM_NEIGHBOURS(c, g)
-    const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(R), (uint32_t)c.x * (uint32_t)sizeof(R),
-                            (uint32_t)xm * (uint32_t)sizeof(R)};
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-      R* row = const_cast<R*>(row_base<L>((const R*)lam_out, q, c.y, c.z, ym, yp, zm, zp, g));
-      *at_bytes(row, ox[L::c(q, 0) + 1]) = lam[q];
-    }
-    if (bb) {
-#pragma unroll
-      for (int q = 1; q < L::Q; ++q)
-        if ((bb >> q) & 1u) lam_out[(size_t)opp<L>(q) * N + c.cell] = lam[q];
-    }
-  }
-  block_sum_adj<3>(dF);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) partials[(size_t)blockIdx.x * 3 + k] += dF[k];
 }
 
 // One lambda array (AA pattern), in place; ODD selects the adjoint of the
@@ -365,38 +317,35 @@ static hipError_t by_stencil_dtype(int stencil, int dtype, F&& fn) {
 }
 
 hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
-                               int layout, const void* force_y, const void* dL_drho, const void* dL_du,
-                               int field_dtype, void* lam, double* partials, const Geo& g, const Params& p,
-                               hipStream_t s) {
+                               int layout, int lam_layout, const void* force_y, const void* dL_drho,
+                               const void* dL_du, int field_dtype, void* lam, double* partials, const Geo& g,
+                               const Params& p, hipStream_t s) {
   return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     using R = typename Storage<T>::R;
     hipLaunchKernelGGL((k_adj_seed<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, layout, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam, partials, g,
-                       p.rho0, (const R*)p.wall);
+                       has_mask, layout, lam_layout, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam,
+                       partials, g, p.rho0, (const R*)p.wall);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
-                                int has_mask, const void* force_y, void* lam_in, void* lam_out, double* partials,
-                                const Geo& g, const Params& p, hipStream_t s) {
+                                int has_mask, const void* force_y, void* lam, double* partials, const Geo& g,
+                                const Params& p, hipStream_t s) {
   return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     using R = typename Storage<T>::R;
     const CollideParams<R> cp = to_collide_params<R>(p);
     const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
-    if (phase < 0)
-      hipLaunchKernelGGL((k_adj_sweep<L, T>), grid, block, 0, s, (const T*)P, flags, has_mask, (const R*)force_y,
-                         (const R*)lam_in, (R*)lam_out, partials, g, cp);
-    else if (phase == 0)
+    if (phase == 0)
       hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 0>), grid, block, 0, s, (const T*)P, flags, has_mask,
-                         (const R*)force_y, (R*)lam_in, partials, g, cp);
+                         (const R*)force_y, (R*)lam, partials, g, cp);
     else
       hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 1>), grid, block, 0, s, (const T*)P, flags, has_mask,
-                         (const R*)force_y, (R*)lam_in, partials, g, cp);
+                         (const R*)force_y, (R*)lam, partials, g, cp);
     return hipGetLastError();
   });
 }

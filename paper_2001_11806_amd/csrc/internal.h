@@ -67,20 +67,20 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 
 // adjoint (adjoint.hip)
 bool adjoint_supported(int stencil, int method);
-// `layout` (seed, init gradient) places lambda like the stored state of the
-// same time (0 two arrays, 1 / 2 AA); the forward state P read by the seed is
-// in that layout too.
+// Layouts as for the stored state (0 two arrays, 1 AA inverted, 2
+// streamed): the seed reads P in `layout` and places lambda in `lam_layout`
+// (the AA layout of the seeded time); the init gradient reads lambda in
+// `layout`.
 hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint8_t* flags,
-                               int has_mask, int layout, const void* force_y, const void* dL_drho,
-                               const void* dL_du, int field_dtype, void* lam, double* partials,
-                               const Geo& g, const Params& p, hipStream_t s);
-// phase -1: two lambda arrays, lam_in -> lam_out; 0 / 1: adjoint of the AA
-// even / odd kernel, in place on lam_in (lam_out unused).  P is the forward
-// state of the reversed step in the two-array layout.
+                               int has_mask, int layout, int lam_layout, const void* force_y,
+                               const void* dL_drho, const void* dL_du, int field_dtype, void* lam,
+                               double* partials, const Geo& g, const Params& p, hipStream_t s);
+// Transpose of one time step: phase 0 / 1 = of the AA even / odd kernel, in
+// place on lam.  P is the forward state of the reversed step in the
+// two-array layout (the tape and the recomputed segment hold that layout).
 hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
-                                int has_mask, const void* force_y, void* lam_in,
-                                void* lam_out, double* partials, const Geo& g, const Params& p,
-                                hipStream_t s);
+                                int has_mask, const void* force_y, void* lam, double* partials,
+                                const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags,
                                     int has_mask, int layout, const void* init_fields, void* dL_du0,
                                     void* dL_drho0, int field_dtype, const Geo& g,

@@ -66,8 +66,7 @@ struct lbm_ctx {
   int64_t seg_id = -1;
   bool tape_ok = false;
   void* init_fields = nullptr; // compute type: rho, ux, uy, uz
-  void* lam[2] = {nullptr, nullptr};
-  int lam_cur = 0;
+  void* lam = nullptr;         // compute type, Q * N: lambda in the AA layout of its time
   int64_t adj_t = -1;
   int64_t adj_T = -1;
   // graph replay for small lattices: one executable graph per starting grid
@@ -85,7 +84,7 @@ void free_ctx(lbm_ctx* c) {
     if (ge) (void)hipGraphExecDestroy(ge);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* bufs[] = {c->grid[0], c->grid[1], c->flags, c->links, c->force,       c->wall,   c->partials, c->acc,
-                  c->adj_acc, c->tape,    c->seg,   c->init_fields, c->lam[0], c->lam[1]};
+                  c->adj_acc, c->tape,    c->seg,   c->init_fields, c->lam};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete c;
@@ -338,8 +337,8 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
     if ((st = alloc(&c->init_fields, 4 * N * rb, "initial fields")) != LBM_OK) return bail(st);
     if ((st = alloc((void**)&c->adj_acc, (size_t)nblk * 3 * sizeof(double), "dL/dF accumulators")) != LBM_OK)
       return bail(st);
-    for (int i = 0; i < (cfg->pattern == 1 ? 1 : 2); ++i)   // AA: the adjoint runs in place too
-      if ((st = alloc(&c->lam[i], (size_t)c->Q * N * rb, "adjoint state")) != LBM_OK) return bail(st);
+    // one lambda array, updated in place by the transposed AA kernels
+    if ((st = alloc(&c->lam, (size_t)c->Q * N * rb, "adjoint state")) != LBM_OK) return bail(st);
   }
   hipError_t e;
   if ((e = launch_fill_zero(c->force, 3 * (size_t)cfg->ny * rb, c->stream)) != hipSuccess)
@@ -553,14 +552,13 @@ int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_d
   if (!ctx->tape_ok) return fail(LBM_ESTATE, "the tape is invalid (force changed after initialisation)");
   if (ctx->t > ctx->cfg.max_tape_steps)
     return fail(LBM_ESTATE, "%lld steps exceed max_tape_steps = %d", (long long)ctx->t, ctx->cfg.max_tape_steps);
-  const size_t lam_bytes = (size_t)ctx->Q * (size_t)ctx->g.N * compute_bytes(ctx->cfg.dtype);
-  if (!is_aa(ctx)) HIP_TRY(launch_fill_zero(ctx->lam[1], lam_bytes, ctx->stream), "adjoint state clear");
-  // the seed writes every slot of lam[0], in the layout of the current state
+  // lambda^T goes into the AA layout of time T (1 after an odd number of
+  // steps, 2 after an even one) whatever the forward pattern; the seed
+  // writes every slot
   HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
-                              layout_of(ctx), ctx->force, dL_drho_dev, dL_du_dev, field_dtype, ctx->lam[0],
-                              ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
+                              layout_of(ctx), (ctx->t & 1) ? 1 : 2, ctx->force, dL_drho_dev, dL_du_dev,
+                              field_dtype, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
           "adjoint seed launch");
-  ctx->lam_cur = 0;
   ctx->adj_T = ctx->t;
   ctx->adj_t = ctx->t;
   ctx->seg_id = -1;
@@ -605,17 +603,10 @@ int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
     const void* P = nullptr;
     int32_t st = forward_state(ctx, s, &P);
     if (st != LBM_OK) return st;
-    if (is_aa(ctx)) {   // adjoint of the even (s even) or odd kernel, in place
-      HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags, ctx->has_mask,
-                                   ctx->force, ctx->lam[0], nullptr, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
-              "AA adjoint sweep launch");
-    } else {
-      HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, -1, P, ctx->flags, ctx->has_mask, ctx->force,
-                                   ctx->lam[ctx->lam_cur], ctx->lam[ctx->lam_cur ^ 1], ctx->adj_acc, ctx->g,
-                                   ctx->p, ctx->stream),
-              "adjoint sweep launch");
-      ctx->lam_cur ^= 1;
-    }
+    // transpose of the AA even (s even) or odd kernel, in place on lambda
+    HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags, ctx->has_mask,
+                                 ctx->force, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
+            "adjoint sweep launch");
     ctx->adj_t -= 1;
   }
   return LBM_OK;
@@ -627,8 +618,8 @@ int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev, in
   if (st != LBM_OK) return st;
   if (ctx->adj_t != 0) return fail(LBM_ESTATE, "the adjoint has not reached t = 0");
   if (dL_du0_dev || dL_drho0_dev)
-    HIP_TRY(launch_adjoint_init_grad(ctx->cfg.stencil, ctx->cfg.dtype, ctx->lam[ctx->lam_cur], ctx->flags,
-                                     ctx->has_mask, is_aa(ctx) ? 2 : 0, ctx->init_fields, dL_du0_dev, dL_drho0_dev,
+    HIP_TRY(launch_adjoint_init_grad(ctx->cfg.stencil, ctx->cfg.dtype, ctx->lam, ctx->flags,
+                                     ctx->has_mask, 2, ctx->init_fields, dL_du0_dev, dL_drho0_dev,
                                      field_dtype, ctx->g, ctx->p, ctx->stream),
             "init gradient launch");
   if (dL_dF) {
