@@ -1,5 +1,5 @@
-"""Tangent-linear and discrete adjoint of the SRT + Guo + bounce-back time
-step (test infrastructure only; see ``oracle/__init__.py``).
+"""Tangent-linear and discrete adjoint of the SRT / TRT / MRT + Guo +
+bounce-back time step (test infrastructure only; see ``oracle/__init__.py``).
 
 The paper does not treat differentiation; this module is derived by hand
 from the forward map that ``run`` implements, compressible Eq. (3)
@@ -8,13 +8,21 @@ equilibrium, uniform body force F:
     P^0      = f^eq(rho_init, u_init)                          (fluid cells)
     g(x)     = pull-gather of P^t with halfway bounce-back      (a permutation)
     rho, u   = sum g,  (sum c g + F/2) / rho
-    P^{t+1}  = g - omega (g - f^eq(rho, u)) + (1 - omega/2) S(u, F)
+    P^{t+1}  = g - A (g - f^eq(rho, u)) + B S(u, F)
     readout  : rho_T = sum P^T,  u_T = (sum c P^T - F/2) / rho_T
 
-Jacobian of the collision at one cell, J[q, p] = dP*_q / dg_p:
+with constant Q x Q matrices: SRT A = omega I, B = (1 - omega/2) I; TRT
+A = omega_e P+ + omega_o P-, B = (1 - omega_e/2) P+ + (1 - omega_o/2) P-
+(P+- the symmetric / antisymmetric parts of each (q, opp q) pair); MRT
+A = M^-1 S M, B = M^-1 (I - S/2) M (rates 0 on the conserved moments), the
+forms ``collision`` evaluates.  Jacobian of the collision at one cell,
+J[q, p] = dP*_q / dg_p:
 
-    (1 - omega) delta_qp + omega f^eq_q / rho
-        + sum_a (omega df^eq_q/du_a + dS_q/du_a) (c_pa - u_a) / rho
+    delta_qp - A_qp + sum_k A_qk [f^eq_k / rho + sum_a df^eq_k/du_a (c_pa - u_a) / rho]
+        + sum_k B_qk sum_a dS_k/du_a (c_pa - u_a) / rho
+
+(SRT: (1 - omega) delta_qp + omega f^eq_q / rho + sum_a (omega df^eq_q/du_a
++ (1 - omega/2) dS_q/du_a) (c_pa - u_a) / rho.)
 
 The adjoint state lambda^t = dL/dP^t is propagated by h = J^T lambda^{t+1}
 at every fluid cell followed by the transpose of the gather (each slot of
@@ -30,8 +38,29 @@ from .lattice import CS2
 from .stream import _shift, stream_pull
 
 
-def _local_derivs(lat, g, omega, F):
-    """rho, u and the per-cell derivative blocks for pre-collision g (Q, n)."""
+def relaxation_matrices(cfg):
+    """The constant matrices A (relaxation) and B (source weighting) of the
+    collision P* = g - A (g - f^eq) + B S for SRT, TRT and MRT."""
+    from .collision import _group_rates, _mrt_tables, trt_odd_rate
+    lat, r = cfg.lat, cfg.rates
+    I = np.eye(lat.Q)
+    if cfg.method == "SRT":
+        return r["omega"] * I, (1.0 - 0.5 * r["omega"]) * I
+    if cfg.method == "TRT":
+        Pi = I[lat.opp]                    # (Pi v)_q = v_opp(q)
+        Pp, Pm = 0.5 * (I + Pi), 0.5 * (I - Pi)
+        we, wo = r["omega"], trt_odd_rate(r)
+        return we * Pp + wo * Pm, (1.0 - 0.5 * we) * Pp + (1.0 - 0.5 * wo) * Pm
+    if cfg.method == "MRT":
+        M, groups, Minv = _mrt_tables(lat.name)
+        s = _group_rates(groups, r)
+        return Minv @ np.diag(s) @ M, Minv @ np.diag(1.0 - 0.5 * s) @ M
+    raise ValueError("no adjoint for " + cfg.method)
+
+
+def _local_derivs(lat, g, F):
+    """rho, u and the per-cell derivative blocks for pre-collision g (Q, n)
+    (S is the Guo source without its rate factor)."""
     c = lat.c.astype(np.float64)                      # (Q, 3)
     F = np.asarray(F, dtype=np.float64).reshape(3, 1)
     rho, j = density_momentum(lat, g)
@@ -44,26 +73,28 @@ def _local_derivs(lat, g, omega, F):
     dfeq_du = (w * rho)[:, None, :] * (c[:, :, None] / CS2
                                        + cu[:, None, :] * c[:, :, None] / CS2 ** 2
                                        - u[None, :, :] / CS2)
-    # dS_q/du_a including (1 - omega/2)   (Q, 3, 1)
-    dS_du = (1 - 0.5 * omega) * w[:, :, None] * (-F.reshape(1, 3, 1) / CS2
-                                                 + c[:, :, None] * cF[:, :, None] / CS2 ** 2)
+    # dS_q/du_a   (Q, 3, 1)
+    dS_du = w[:, :, None] * (-F.reshape(1, 3, 1) / CS2 + c[:, :, None] * cF[:, :, None] / CS2 ** 2)
     dS_du = np.broadcast_to(dS_du, dfeq_du.shape)
-    # dS_q/dF_b at fixed u, including (1 - omega/2)   (Q, 3, n)
-    dS_dF = (1 - 0.5 * omega) * w[:, :, None] * ((c[:, :, None] - u[None, :, :]) / CS2
-                                                 + cu[:, None, :] * c[:, :, None] / CS2 ** 2)
+    # dS_q/dF_b at fixed u   (Q, 3, n)
+    dS_dF = w[:, :, None] * ((c[:, :, None] - u[None, :, :]) / CS2 + cu[:, None, :] * c[:, :, None] / CS2 ** 2)
     return rho, u, feq, dfeq_du, dS_du, dS_dF
 
 
-def collision_jacobian(lat, g, omega, F):
+def collision_jacobian(cfg, g, F):
     """J[q, p, n] = dP*_q/dg_p and B[q, b, n] = dP*_q/dF_b at each cell."""
-    rho, u, feq, dfeq_du, dS_du, dS_dF = _local_derivs(lat, g, omega, F)
+    lat = cfg.lat
+    Amat, Bmat = relaxation_matrices(cfg)
+    rho, u, feq, dfeq_du, dS_du, dS_dF = _local_derivs(lat, g, F)
     c = lat.c.astype(np.float64)
     du_dg = (c.T[:, :, None] - u[:, None, :]) / rho   # (3, Q_p, n)
-    A = omega * dfeq_du + dS_du                       # (Q, 3, n)
-    J = np.einsum("qan,apn->qpn", A, du_dg)
-    J = J + omega * (feq / rho)[:, None, :]
-    J = J + (1.0 - omega) * np.eye(lat.Q)[:, :, None]
-    B = dS_dF + A / (2.0 * rho)
+    dfeq_dg = np.einsum("kan,apn->kpn", dfeq_du, du_dg) + (feq / rho)[:, None, :]
+    dS_dg = np.einsum("kan,apn->kpn", dS_du, du_dg)
+    J = (np.eye(lat.Q) - Amat)[:, :, None] + np.einsum("qk,kpn->qpn", Amat, dfeq_dg) \
+        + np.einsum("qk,kpn->qpn", Bmat, dS_dg)
+    # dP*/dF: the source at fixed u, and u = (j + F/2) / rho
+    du_term = np.einsum("qk,kan->qan", Amat, dfeq_du) + np.einsum("qk,kan->qan", Bmat, dS_du)
+    B = np.einsum("qk,kbn->qbn", Bmat, dS_dF) + du_term / (2.0 * rho)
     return J, B
 
 
@@ -75,10 +106,10 @@ def trajectory(cfg, rho_init, u_init, solid, F, T, wall_velocity=None):
     P = np.where(s[None], lat.w.reshape(-1, 1, 1, 1) * cfg.rho0, P)
     Ps = [P]
     Ff = np.broadcast_to(np.asarray(F, float).reshape(3, 1, 1, 1), (3,) + s.shape)
-    from .collision import srt
+    from .collision import collide
     for _ in range(T):
         g = stream_pull(lat, P, solid, wall_velocity, cfg.rho0)
-        post = srt(lat, g, cfg.rates, Ff)
+        post = collide(cfg.method, lat, g, cfg.rates, Ff, cfg.rho0, cfg.compressible)
         P = np.where(s[None], P, post)
         Ps.append(P)
     return Ps
@@ -129,7 +160,7 @@ def adjoint_step(cfg, P_t, lam_next, solid, F, wall_velocity=None):
     fl = ~s
     g = stream_pull(lat, P_t, solid, wall_velocity, cfg.rho0)
     shp = g.shape[1:]
-    J, B = collision_jacobian(lat, g.reshape(lat.Q, -1), cfg.rates["omega"], F)
+    J, B = collision_jacobian(cfg, g.reshape(lat.Q, -1), F)
     lam2 = lam_next.reshape(lat.Q, -1)
     h = np.einsum("qpn,qn->pn", J, lam2).reshape(g.shape)
     dF_cell = np.einsum("qbn,qn->bn", B, lam2).reshape((3,) + shp)
@@ -194,7 +225,7 @@ def tangent(cfg, rho_init, u_init, solid, F, T, du0, dF, loss=outlet_loss, wall_
     for t in range(T):
         g = stream_pull(lat, Ps[t], solid, wall_velocity, cfg.rho0)
         dg = stream_pull(lat, dP, s)
-        J, B = collision_jacobian(lat, g.reshape(lat.Q, -1), cfg.rates["omega"], F)
+        J, B = collision_jacobian(cfg, g.reshape(lat.Q, -1), F)
         new = np.einsum("qpn,pn->qn", J, dg.reshape(lat.Q, -1)) + np.einsum("qbn,b->qn", B, dFv)
         dP = np.where(s[None], dP, new.reshape(dP.shape))
     L, dL_du = loss(cfg, Ps[T], solid, F)

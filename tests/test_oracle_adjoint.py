@@ -9,8 +9,14 @@ from oracle import adjoint, run
 from paper_2001_11806_amd import inputs
 
 
-def _setup(nx=8, ny=10, nz=6, T=12, seed=4):
-    cfg = run.Config("D3Q19", "SRT", dict(omega=1 / 0.6))
+RATES = {"SRT": dict(omega=1 / 0.6),
+         "TRT": dict(omega=1 / 0.6, magic=3 / 16, omega_odd=0.0),
+         "MRT": dict(omega=1 / 0.6, omega_bulk=1.2, omega_hi=(1.3, 0.9, 1.1, 1.2))}
+METHODS = ["SRT", "TRT", "MRT"]
+
+
+def _setup(nx=8, ny=10, nz=6, T=12, seed=4, method="SRT"):
+    cfg = run.Config("D3Q19", method, RATES[method])
     mask = inputs.channel_mask(nx, ny, nz)
     mask[2:4, 4:6, 3:5] = 1                      # a small obstacle
     u0 = inputs.uniform_noise_velocity((nx, ny, nz), 2e-2, seed, mask)
@@ -24,17 +30,19 @@ def _loss(cfg, rho, u0, mask, F, T):
     return adjoint.outlet_loss(cfg, Ps[T], mask, F)[0]
 
 
-def test_trajectory_equals_run_step():
+@pytest.mark.parametrize("method", METHODS)
+def test_trajectory_equals_run_step(method):
     """The adjoint module's forward trajectory is the ordinary time step."""
-    cfg, mask, rho, u0, F, T = _setup(T=5)
+    cfg, mask, rho, u0, F, T = _setup(T=5, method=method)
     Ps = adjoint.trajectory(cfg, rho, u0, mask, F, T)
     P = run.init_equilibrium(cfg, rho, u0, mask)
     P = run.run(cfg, P, T, mask, run.force_field(F, (8, 10, 6)))
     np.testing.assert_array_equal(Ps[T], P)
 
 
-def test_tangent_matches_central_differences():
-    cfg, mask, rho, u0, F, T = _setup()
+@pytest.mark.parametrize("method", METHODS)
+def test_tangent_matches_central_differences(method):
+    cfg, mask, rho, u0, F, T = _setup(method=method)
     rng = np.random.default_rng(1)
     du = rng.standard_normal(u0.shape) * (mask == 0)
     dF = rng.standard_normal(3)
@@ -45,9 +53,10 @@ def test_tangent_matches_central_differences():
     assert abs(tl / fd - 1) < 1e-6
 
 
-def test_adjoint_dot_product_identity():
+@pytest.mark.parametrize("method", METHODS)
+def test_adjoint_dot_product_identity(method):
     """<dL/dp, v> from the reverse sweep equals the tangent along v."""
-    cfg, mask, rho, u0, F, T = _setup()
+    cfg, mask, rho, u0, F, T = _setup(method=method)
     L, gu, grho, gF = adjoint.gradient(cfg, rho, u0, mask, F, T)
     rng = np.random.default_rng(2)
     for _ in range(3):
@@ -58,8 +67,9 @@ def test_adjoint_dot_product_identity():
         assert abs(rev / tl - 1) < 1e-12
 
 
-def test_gradient_matches_finite_differences_and_taylor_order():
-    cfg, mask, rho, u0, F, T = _setup()
+@pytest.mark.parametrize("method", METHODS)
+def test_gradient_matches_finite_differences_and_taylor_order(method):
+    cfg, mask, rho, u0, F, T = _setup(method=method)
     L, gu, grho, gF = adjoint.gradient(cfg, rho, u0, mask, F, T)
     rng = np.random.default_rng(3)
     fluid = np.argwhere((mask == 0))
@@ -115,3 +125,23 @@ def test_moving_wall_gradient_matches_finite_differences():
     e[0, 2, 5, 7] = 1.0
     fd = (loss(u0 + h * e, F) - loss(u0 - h * e, F)) / (2 * h)
     assert abs(gu[0, 2, 5, 7] - fd) <= 1e-6 * abs(fd) + 1e-11
+
+
+def test_relaxation_matrices_reproduce_the_collisions():
+    """P* = g - A (g - f^eq) + B S with the adjoint's constant matrices is the
+    collision the forward run applies (SRT, TRT, MRT), so the Jacobian is
+    taken of the right map."""
+    from oracle import collision
+    from oracle.equilibrium import equilibrium, guo_source, macroscopic
+    rng = np.random.default_rng(6)
+    for method in METHODS:
+        cfg = run.Config("D3Q19", method, RATES[method])
+        lat = cfg.lat
+        rho = 1 + 0.01 * rng.uniform(-1, 1, 20)
+        u = 0.03 * rng.uniform(-1, 1, (3, 20))
+        g = equilibrium(lat, rho, u) * (1 + 0.05 * rng.uniform(-1, 1, (lat.Q, 20)))
+        F = 1e-3 * rng.uniform(-1, 1, (3, 20))
+        A, B = adjoint.relaxation_matrices(cfg)
+        r, uu = macroscopic(lat, g, F)
+        want = g - A @ (g - equilibrium(lat, r, uu)) + B @ guo_source(lat, uu, F)
+        np.testing.assert_allclose(collision.collide(method, lat, g, cfg.rates, F), want, rtol=0, atol=1e-15)
