@@ -27,11 +27,15 @@
 // to, (x + c_q, q) or (x, opp q) at a wall, and writes h to the slots it
 // pulled from, (x - c_q, opp q) or (x, q) at a wall.  Both run in place
 // without races, and lambda needs one array instead of two.
+#include <type_traits>
+
 #include "sweep.h"
 
 namespace lbm {
 
-bool adjoint_supported(int stencil, int method) { return method == M_SRT && stencil >= 0 && stencil <= 2; }
+bool adjoint_supported(int stencil, int method) {
+  return (method == M_SRT || method == M_TRT) && stencil >= 0 && stencil <= 2;
+}
 
 template <int W>
 __device__ __forceinline__ void block_sum_adj(double (&v)[W]) {
@@ -140,10 +144,44 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
 }
 
 // ------------------------------------------------------------------ sweep
+// a = A^T lambda and b = B^T lambda for the collision's constant matrices
+// (P* = g - A (g - f^eq) + B S): SRT A = omega I, B = (1 - omega/2) I; TRT
+// A = omega_e P+ + omega_o P-, B = (1 - omega_e/2) P+ + (1 - omega_o/2) P-,
+// with P+- the symmetric and antisymmetric parts of each (q, opp q) pair
+// (symmetric matrices, so A^T = A).
+template <class L, int M, class R>
+__device__ __forceinline__ void relax_transpose(const R* lam, R* a, R* b, const CollideParams<R>& p) {
+  if constexpr (M == M_TRT) {
+    const R we = p.om, wo = p.om_o, fe = R(1) - R(0.5) * we, fo = R(1) - R(0.5) * wo;
+    a[0] = we * lam[0];
+    b[0] = fe * lam[0];
+#pragma unroll
+    for (int q = 1; q <= L::H; ++q) {
+      const int o = q + L::H;
+      const R lp = R(0.5) * (lam[q] + lam[o]), lm = R(0.5) * (lam[q] - lam[o]);
+      a[q] = we * lp + wo * lm;
+      a[o] = we * lp - wo * lm;
+      b[q] = fe * lp + fo * lm;
+      b[o] = fe * lp - fo * lm;
+    }
+  } else {
+    const R om = p.om, fs = R(1) - R(0.5) * p.om;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      a[q] = om * lam[q];
+      b[q] = fs * lam[q];
+    }
+  }
+}
+
 // One fluid cell: lam (lambda^{t+1} of the cell, Q values) becomes h = J^T lam
 // in place, for the pre-collision populations f; dF receives the cell's
-// dL/dF contribution.
-template <class L, class R>
+// dL/dF contribution.  With a = A^T lam, b = B^T lam:
+//   h_p = lam_p - a_p + alpha + (c_p - u).beta / rho,
+//   alpha = sum_q a_q f^eq_q / rho,
+//   beta  = sum_q [a_q df^eq_q/du + b_q dS_q/du],
+//   dL/dF += sum_q b_q dS_q/dF (at fixed u) + beta / (2 rho).
+template <class L, int M, class R>
 __device__ __forceinline__ void adj_cell(const R* f, R* lam, R F0, R F1, R F2, const CollideParams<R>& p,
                                          double* dF) {
   R drho, jx, jy, jz;
@@ -152,19 +190,55 @@ __device__ __forceinline__ void adj_cell(const R* f, R* lam, R F0, R F1, R F2, c
   const R inv = R(1) / rho;
   const R ux = (jx + R(0.5) * F0) * inv, uy = (jy + R(0.5) * F1) * inv, uz = (jz + R(0.5) * F2) * inv;
   const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
-  const R om = p.om, fs = R(1) - R(0.5) * p.om;
-  const R omr3 = R(3) * om * rho;
-  R alpha = R(0), s0 = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
+  if constexpr (M == M_SRT) {   // a = omega lam, b = (1 - omega/2) lam: the factors come out of the sums
+    const R om = p.om, fs = R(1) - R(0.5) * p.om;
+    const R omr3 = R(3) * om * rho;
+    R alpha = R(0), s0 = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const R w = R(weight<L>(q));
+      const R cu = cdot<L>(q, ux, uy, uz);
+      const R cF = cdot<L>(q, F0, F1, F2);
+      const R lw = lam[q] * w;
+      alpha += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+      s0 += lw;
+      const R t = lw * (omr3 * (R(1) + R(3) * cu) + R(9) * fs * cF);
+      const R sf = lw * (R(3) + R(9) * cu);
+      if (L::c(q, 0) == 1) { bx += t; sx += sf; }
+      if (L::c(q, 0) == -1) { bx -= t; sx -= sf; }
+      if (L::c(q, 1) == 1) { by += t; sy += sf; }
+      if (L::c(q, 1) == -1) { by -= t; sy -= sf; }
+      if (L::c(q, 2) == 1) { bz += t; sz += sf; }
+      if (L::c(q, 2) == -1) { bz -= t; sz -= sf; }
+    }
+    alpha *= om;
+    bx -= R(3) * (om * rho * ux + fs * F0) * s0;
+    by -= R(3) * (om * rho * uy + fs * F1) * s0;
+    bz -= R(3) * (om * rho * uz + fs * F2) * s0;
+    const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
+    const R one_m = R(1) - om;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) lam[q] = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
+    dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
+    dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
+    dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
+    return;
+  }
+  R a[L::Q], b[L::Q];
+  relax_transpose<L, M, R>(lam, a, b, p);
+  const R r3 = R(3) * rho;
+  R alpha = R(0), sa = R(0), sb = R(0), bx = R(0), by = R(0), bz = R(0), sx = R(0), sy = R(0), sz = R(0);
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     const R w = R(weight<L>(q));
     const R cu = cdot<L>(q, ux, uy, uz);
     const R cF = cdot<L>(q, F0, F1, F2);
-    const R lw = lam[q] * w;
-    alpha += lw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
-    s0 += lw;
-    const R t = lw * (omr3 * (R(1) + R(3) * cu) + R(9) * fs * cF);
-    const R sf = lw * (R(3) + R(9) * cu);
+    const R aw = a[q] * w, bw = b[q] * w;
+    alpha += aw * (R(1) + R(3) * cu + R(4.5) * cu * cu - usq);
+    sa += aw;
+    sb += bw;
+    const R t = aw * (r3 * (R(1) + R(3) * cu)) + bw * (R(9) * cF);
+    const R sf = bw * (R(3) + R(9) * cu);
     if (L::c(q, 0) == 1) { bx += t; sx += sf; }
     if (L::c(q, 0) == -1) { bx -= t; sx -= sf; }
     if (L::c(q, 1) == 1) { by += t; sy += sf; }
@@ -172,23 +246,21 @@ __device__ __forceinline__ void adj_cell(const R* f, R* lam, R F0, R F1, R F2, c
     if (L::c(q, 2) == 1) { bz += t; sz += sf; }
     if (L::c(q, 2) == -1) { bz -= t; sz -= sf; }
   }
-  alpha *= om;
-  bx -= R(3) * (om * rho * ux + fs * F0) * s0;
-  by -= R(3) * (om * rho * uy + fs * F1) * s0;
-  bz -= R(3) * (om * rho * uz + fs * F2) * s0;
+  bx -= r3 * ux * sa + R(3) * F0 * sb;
+  by -= r3 * uy * sa + R(3) * F1 * sb;
+  bz -= r3 * uz * sa + R(3) * F2 * sb;
   const R base = alpha - (bx * ux + by * uy + bz * uz) * inv;
-  const R one_m = R(1) - om;
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) lam[q] = one_m * lam[q] + base + cdot<L>(q, bx, by, bz) * inv;
-  dF[0] = (double)(fs * (sx - R(3) * ux * s0) + bx * R(0.5) * inv);
-  dF[1] = (double)(fs * (sy - R(3) * uy * s0) + by * R(0.5) * inv);
-  dF[2] = (double)(fs * (sz - R(3) * uz * s0) + bz * R(0.5) * inv);
+  for (int q = 0; q < L::Q; ++q) lam[q] = lam[q] - a[q] + base + cdot<L>(q, bx, by, bz) * inv;
+  dF[0] = (double)(sx - R(3) * ux * sb + bx * R(0.5) * inv);
+  dF[1] = (double)(sy - R(3) * uy * sb + by * R(0.5) * inv);
+  dF[2] = (double)(sz - R(3) * uz * sb + bz * R(0.5) * inv);
 }
 
 // One lambda array (AA pattern), in place; ODD selects the adjoint of the
 // odd kernel.  P is the forward state of the reversed step in the two-array
 // layout (the tape and the recomputed segment hold that layout).
-template <class L, class T, int ODD>
+template <class L, class T, int ODD, int M>
 __global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                       int has_mask,
                                                       const typename Storage<T>::R* __restrict__ force_y,
@@ -223,7 +295,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, c
           if ((bb >> opp<L>(q)) & 1u) lam[q] = *at_bytes(own + (size_t)opp<L>(q) * N, ox[1]);
       }
     }
-    adj_cell<L, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
+    adj_cell<L, M, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
     if (!ODD) {
 #pragma unroll
       for (int q = 0; q < L::Q; ++q) *at_bytes(own + (size_t)q * N, ox[1]) = lam[q];
@@ -331,21 +403,28 @@ hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint
   });
 }
 
-hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
-                                int has_mask, const void* force_y, void* lam, double* partials, const Geo& g,
-                                const Params& p, hipStream_t s) {
+hipError_t launch_adjoint_sweep(int stencil, int method, int dtype, int phase, const void* P,
+                                const uint8_t* flags, int has_mask, const void* force_y, void* lam,
+                                double* partials, const Geo& g, const Params& p, hipStream_t s) {
   return by_stencil_dtype(stencil, dtype, [&](auto lat, auto tag) -> hipError_t {
     using L = decltype(lat);
     using T = decltype(tag);
     using R = typename Storage<T>::R;
     const CollideParams<R> cp = to_collide_params<R>(p);
     const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
-    if (phase == 0)
-      hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 0>), grid, block, 0, s, (const T*)P, flags, has_mask,
-                         (const R*)force_y, (R*)lam, partials, g, cp);
-    else
-      hipLaunchKernelGGL((k_adj_sweep_aa<L, T, 1>), grid, block, 0, s, (const T*)P, flags, has_mask,
-                         (const R*)force_y, (R*)lam, partials, g, cp);
+    auto go = [&](auto odd, auto meth) {
+      hipLaunchKernelGGL((k_adj_sweep_aa<L, T, decltype(odd)::value, decltype(meth)::value>), grid, block, 0, s,
+                         (const T*)P, flags, has_mask, (const R*)force_y, (R*)lam, partials, g, cp);
+    };
+    using Z = std::integral_constant<int, 0>;
+    using O = std::integral_constant<int, 1>;
+    using SRT = std::integral_constant<int, M_SRT>;
+    using TRT = std::integral_constant<int, M_TRT>;
+    if (method == M_TRT) {
+      if (phase == 0) go(Z(), TRT()); else go(O(), TRT());
+    } else {
+      if (phase == 0) go(Z(), SRT()); else go(O(), SRT());
+    }
     return hipGetLastError();
   });
 }

@@ -78,9 +78,9 @@ hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint
 // Transpose of one time step: phase 0 / 1 = of the AA even / odd kernel, in
 // place on lam.  P is the forward state of the reversed step in the
 // two-array layout (the tape and the recomputed segment hold that layout).
-hipError_t launch_adjoint_sweep(int stencil, int dtype, int phase, const void* P, const uint8_t* flags,
-                                int has_mask, const void* force_y, void* lam, double* partials,
-                                const Geo& g, const Params& p, hipStream_t s);
+hipError_t launch_adjoint_sweep(int stencil, int method, int dtype, int phase, const void* P,
+                                const uint8_t* flags, int has_mask, const void* force_y, void* lam,
+                                double* partials, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_adjoint_init_grad(int stencil, int dtype, const void* lam, const uint8_t* flags,
                                     int has_mask, int layout, const void* init_fields, void* dL_du0,
                                     void* dL_drho0, int field_dtype, const Geo& g,

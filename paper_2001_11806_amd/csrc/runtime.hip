@@ -149,7 +149,7 @@ int32_t validate(const lbm_config* cfg) {
   if (cfg->checkpoint_every > 0) {
     if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
     if (!adjoint_supported(cfg->stencil, cfg->method) || !cfg->compressible)
-      return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT method only");
+      return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT and TRT methods only");
   }
   return LBM_OK;
 }
@@ -604,8 +604,8 @@ int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
     int32_t st = forward_state(ctx, s, &P);
     if (st != LBM_OK) return st;
     // transpose of the AA even (s even) or odd kernel, in place on lambda
-    HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags, ctx->has_mask,
-                                 ctx->force, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
+    HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->kmethod, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags,
+                                 ctx->has_mask, ctx->force, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
             "adjoint sweep launch");
     ctx->adj_t -= 1;
   }

@@ -13,6 +13,7 @@ from paper_2001_11806_amd.autograd import LBMFunction
 pytestmark = pytest.mark.gpu
 
 RATES = dict(omega=1 / 0.6, omega_bulk=1.0, omega_odd=0.0, magic=0.0, omega_hi=(1.0,) * 4)
+METHOD_RATES = {"SRT": RATES, "TRT": dict(RATES, magic=3 / 16)}
 
 
 def _case(stencil="D3Q19", dims=(70, 10, 6), T=13, seed=4):
@@ -29,12 +30,12 @@ def _case(stencil="D3Q19", dims=(70, 10, 6), T=13, seed=4):
     return mask, rho, u0, F, T
 
 
-def _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0):
-    g = make_gpu(stencil, "SRT", dtype, dims, mask, RATES, checkpoint_every=k, max_tape_steps=T, pattern=pattern)
+def _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0, method="SRT"):
+    g = make_gpu(stencil, method, dtype, dims, mask, METHOD_RATES[method], checkpoint_every=k, max_tape_steps=T,
+                 pattern=pattern)
     g.set_force(F)
     g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
     g.step(T)
-    cfg = orun.Config(stencil, "SRT", RATES)
     # loss gradient at the GPU's own final state, as the oracle would seed it
     _, u_T = g.macroscopic()
     dL_du = torch.zeros_like(u_T)
@@ -47,27 +48,29 @@ def _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0):
     return to_np(du), to_np(drho), dF
 
 
+@pytest.mark.parametrize("method", ["SRT", "TRT"])
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("k", [1, 4, 13])
-def test_adjoint_fp64_matches_oracle(stencil, k):
+def test_adjoint_fp64_matches_oracle(stencil, k, method):
     need_gpu()
     dims = (70, 10, 1) if stencil == "D2Q9" else (70, 10, 6)
     mask, rho, u0, F, T = _case(stencil, dims)
-    print("case", stencil, "k", k, flush=True)
-    du, drho, dF = _gpu_gradient(stencil, "f64", dims, mask, rho, u0, F, T, k)
-    cfg = orun.Config(stencil, "SRT", RATES)
+    print("case", stencil, method, "k", k, flush=True)
+    du, drho, dF = _gpu_gradient(stencil, "f64", dims, mask, rho, u0, F, T, k, method=method)
+    cfg = orun.Config(stencil, method, METHOD_RATES[method])
     L, gu, grho, gF = oadj.gradient(cfg, rho, u0, mask, F, T)
     assert rel_l2(du, gu) <= 1e-10
     assert rel_l2(drho, grho) <= 1e-10
     np.testing.assert_allclose(dF, gF, rtol=1e-10)
 
 
-def test_adjoint_fp32_matches_oracle():
+@pytest.mark.parametrize("method", ["SRT", "TRT"])
+def test_adjoint_fp32_matches_oracle(method):
     need_gpu()
     dims = (70, 10, 6)
     mask, rho, u0, F, T = _case("D3Q19", dims)
-    du, drho, dF = _gpu_gradient("D3Q19", "f32", dims, mask, rho, u0, F, T, 5)
-    cfg = orun.Config("D3Q19", "SRT", RATES)
+    du, drho, dF = _gpu_gradient("D3Q19", "f32", dims, mask, rho, u0, F, T, 5, method=method)
+    cfg = orun.Config("D3Q19", method, METHOD_RATES[method])
     L, gu, grho, gF = oadj.gradient(cfg, rho, u0, mask, F, T)
     e_u, e_F = rel_l2(du, gu), rel_l2(dF, gF)
     print("fp32 adjoint: rel L2 dL/du0 %.2e, dL/dF %.2e" % (e_u, e_F))
@@ -141,10 +144,11 @@ def test_adjoint_with_moving_wall_matches_oracle():
     np.testing.assert_allclose(dF, gF, rtol=1e-10)
 
 
+@pytest.mark.parametrize("method", ["SRT", "TRT"])
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("T,k", [(13, 4), (12, 5), (7, 1)])
-def test_aa_adjoint_equals_two_arrays(stencil, dtype, T, k):
+def test_aa_adjoint_equals_two_arrays(stencil, dtype, T, k, method):
     """AA pattern with a tape: the checkpoints are stored in the two-array
     layout and lambda is updated in place by the transposed AA kernels.  The
     recomputed states and every per-cell transpose are the two-array ones, so
@@ -152,9 +156,9 @@ def test_aa_adjoint_equals_two_arrays(stencil, dtype, T, k):
     need_gpu()
     dims = (70, 10, 1) if stencil == "D2Q9" else (70, 10, 6)
     mask, rho, u0, F, _ = _case(stencil, dims)
-    print("case AA adjoint", stencil, dtype, "T", T, "k", k, flush=True)
-    a = _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0)
-    b = _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=1)
+    print("case AA adjoint", stencil, method, dtype, "T", T, "k", k, flush=True)
+    a = _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0, method=method)
+    b = _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=1, method=method)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert np.array_equal(np.asarray(a[2]), np.asarray(b[2]))
 
