@@ -23,8 +23,9 @@ collision    SRT (Eq. 1), TRT (Sec. III-C), MRT (Eq. 4),
              entropic KBC (Sec. III-C "Entropic KBC Models")
 stream       pull streaming, halfway bounce-back (Sec. IV-B, Fig. stream-pull)
 run          initialisation, time stepping, readout, storage rounding
-adjoint      tangent-linear and discrete-adjoint maps of the SRT+Guo+bounce-back
-             time step (not in the paper; derived by hand from the forward map)
+adjoint      tangent-linear and discrete-adjoint maps of the SRT / TRT / MRT +
+             Guo + bounce-back time step (not in the paper; derived by hand
+             from the forward map)
 
 Functions without an independent pin say "parity unpinned" in their
 docstring.  All functions listed above are pinned by ``tests/test_oracle_*.py``.
