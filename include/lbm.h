@@ -115,8 +115,8 @@ typedef struct {
  *   omega_h = 1 + [(1 - omega) <ds, dh>_E + (1 - omega_bulk) <db, dh>_E] / <dh, dh>_E,
  *   <a, b>_E = sum_q a_q b_q / f^eq_q, ds / db / dh the shear, bulk and
  *   higher-order parts of f - f^eq; omega_h = 1 when dh = 0);
- * both patterns for every method; the adjoint tape for compressible SRT and
- * TRT with either pattern.  Others return LBM_EUNSUPPORTED. */
+ * both patterns for every method; the adjoint tape for compressible SRT, TRT
+ * and MRT with either pattern.  Others return LBM_EUNSUPPORTED. */
 
 /* Create a context: validates cfg, allocates two PDF grids (plus the tape when
  * checkpoint_every > 0) and copies the solid mask in.
@@ -179,7 +179,7 @@ int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
 /* Number of steps taken since the last init / set_pdfs. */
 int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t);
 
-/* ---- discrete adjoint (SRT and TRT, compressible) -----------------------
+/* ---- discrete adjoint (SRT, TRT and MRT, compressible) ------------------
  * Forward map: P^0 = f^eq(rho_init, u_init) from lbm_init_equilibrium,
  * P^{t+1} = collide(pull-gather(P^t)), readout as lbm_get_macroscopic.
  * The adjoint state lambda^t = dL/dP^t runs backwards through the transposed

@@ -34,7 +34,7 @@
 namespace lbm {
 
 bool adjoint_supported(int stencil, int method) {
-  return (method == M_SRT || method == M_TRT) && stencil >= 0 && stencil <= 2;
+  return (method == M_SRT || method == M_TRT || method == M_MRT) && stencil >= 0 && stencil <= 2;
 }
 
 template <int W>
@@ -148,7 +148,12 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
 // (P* = g - A (g - f^eq) + B S): SRT A = omega I, B = (1 - omega/2) I; TRT
 // A = omega_e P+ + omega_o P-, B = (1 - omega_e/2) P+ + (1 - omega_o/2) P-,
 // with P+- the symmetric and antisymmetric parts of each (q, opp q) pair
-// (symmetric matrices, so A^T = A).
+// (symmetric matrices, so A^T = A); MRT A = M^-1 S M, B = M^-1 (I - S/2) M
+// in the weighted-orthogonal basis, where M^-1 = W M^T D^-1 gives
+//   (A^T lambda)_p = sum_k m_k(c_p) s_k (sum_q m_k(c_q) w_q lambda_q) / d_k,
+// d_k = sum_q w_q m_k(c_q)^2, s_k the rate of row k (0 on conserved rows);
+// the same basis the forward MRT operator relaxes in (on D2Q9 and D3Q27 the
+// forward kernel uses the equivalent tensor-product form).
 template <class L, int M, class R>
 __device__ __forceinline__ void relax_transpose(const R* lam, R* a, R* b, const CollideParams<R>& p) {
   if constexpr (M == M_TRT) {
@@ -163,6 +168,37 @@ __device__ __forceinline__ void relax_transpose(const R* lam, R* a, R* b, const 
       a[o] = we * lp - wo * lm;
       b[q] = fe * lp + fo * lm;
       b[o] = fe * lp - fo * lm;
+    }
+  } else if constexpr (M == M_MRT) {
+    constexpr MrtBasis<L::Q> B = make_mrt_basis<L>();
+    R mom[L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      R acc = R(0);
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q)
+        if (B.m[k][q] != 0.0) acc += R(B.m[k][q] * weight<L>(q)) * lam[q];
+      mom[k] = acc * R(B.inv_norm[k]);
+    }
+    R sa[L::Q], sbv[L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      const int grp = B.group[k];
+      const R rate = grp == 0 ? R(0) : (grp == 1 ? p.om : (grp == 2 ? p.om_b : p.hi[grp - 3]));
+      sa[k] = rate * mom[k];
+      sbv[k] = (R(1) - R(0.5) * rate) * mom[k];
+    }
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      R x = R(0), y = R(0);
+#pragma unroll
+      for (int k = 0; k < L::Q; ++k)
+        if (B.m[k][q] != 0.0) {
+          x += R(B.m[k][q]) * sa[k];
+          y += R(B.m[k][q]) * sbv[k];
+        }
+      a[q] = x;
+      b[q] = y;
     }
   } else {
     const R om = p.om, fs = R(1) - R(0.5) * p.om;
@@ -420,8 +456,11 @@ hipError_t launch_adjoint_sweep(int stencil, int method, int dtype, int phase, c
     using O = std::integral_constant<int, 1>;
     using SRT = std::integral_constant<int, M_SRT>;
     using TRT = std::integral_constant<int, M_TRT>;
+    using MRT = std::integral_constant<int, M_MRT>;
     if (method == M_TRT) {
       if (phase == 0) go(Z(), TRT()); else go(O(), TRT());
+    } else if (method == M_MRT) {
+      if (phase == 0) go(Z(), MRT()); else go(O(), MRT());
     } else {
       if (phase == 0) go(Z(), SRT()); else go(O(), SRT());
     }

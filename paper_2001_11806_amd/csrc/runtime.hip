@@ -149,7 +149,7 @@ int32_t validate(const lbm_config* cfg) {
   if (cfg->checkpoint_every > 0) {
     if (cfg->max_tape_steps < 1) return fail(LBM_EINVAL, "max_tape_steps must be >= 1 with a tape");
     if (!adjoint_supported(cfg->stencil, cfg->method) || !cfg->compressible)
-      return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT and TRT methods only");
+      return fail(LBM_EUNSUPPORTED, "the adjoint is implemented for the compressible SRT, TRT and MRT methods only");
   }
   return LBM_OK;
 }

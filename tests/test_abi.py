@@ -81,12 +81,13 @@ def _create(lib, **kw):
     (dict(method="KBC", cs_smag=0.1), B.EUNSUPPORTED, "Smagorinsky"),
     (dict(method="KBC", checkpoint_every=2, max_tape_steps=4), B.EUNSUPPORTED, "adjoint"),
     (dict(pattern=2), B.EINVAL, "pattern"),
-    (dict(pattern=1, method="MRT", checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
+    (dict(pattern=1, method="CUMULANT", stencil="D3Q27", checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED,
+     "adjoint"),
     (dict(launch_mode=3), B.EINVAL, "launch_mode"),
     (dict(cs_smag=-0.1), B.EINVAL, "cs_smag"),
     (dict(method="TRT", magic=3 / 16, cs_smag=0.1), B.EUNSUPPORTED, "Smagorinsky"),
     (dict(cs_smag=0.1, checkpoint_every=2, max_tape_steps=4), B.EUNSUPPORTED, "Smagorinsky"),
-    (dict(method="MRT", checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
+    (dict(method="KBC", omega_bulk=1.2, checkpoint_every=5, max_tape_steps=10), B.EUNSUPPORTED, "adjoint"),
     (dict(checkpoint_every=5, max_tape_steps=0), B.EINVAL, "max_tape_steps"),
     (dict(checkpoint_every=-1), B.EINVAL, "checkpoint_every"),
 ])

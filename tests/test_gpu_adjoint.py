@@ -13,7 +13,8 @@ from paper_2001_11806_amd.autograd import LBMFunction
 pytestmark = pytest.mark.gpu
 
 RATES = dict(omega=1 / 0.6, omega_bulk=1.0, omega_odd=0.0, magic=0.0, omega_hi=(1.0,) * 4)
-METHOD_RATES = {"SRT": RATES, "TRT": dict(RATES, magic=3 / 16)}
+METHOD_RATES = {"SRT": RATES, "TRT": dict(RATES, magic=3 / 16),
+                "MRT": dict(RATES, omega_bulk=1.2, omega_hi=(1.3, 0.9, 1.1, 1.2))}
 
 
 def _case(stencil="D3Q19", dims=(70, 10, 6), T=13, seed=4):
@@ -48,7 +49,7 @@ def _gpu_gradient(stencil, dtype, dims, mask, rho, u0, F, T, k, pattern=0, metho
     return to_np(du), to_np(drho), dF
 
 
-@pytest.mark.parametrize("method", ["SRT", "TRT"])
+@pytest.mark.parametrize("method", ["SRT", "TRT", "MRT"])
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("k", [1, 4, 13])
 def test_adjoint_fp64_matches_oracle(stencil, k, method):
@@ -64,7 +65,7 @@ def test_adjoint_fp64_matches_oracle(stencil, k, method):
     np.testing.assert_allclose(dF, gF, rtol=1e-10)
 
 
-@pytest.mark.parametrize("method", ["SRT", "TRT"])
+@pytest.mark.parametrize("method", ["SRT", "TRT", "MRT"])
 def test_adjoint_fp32_matches_oracle(method):
     need_gpu()
     dims = (70, 10, 6)
@@ -144,7 +145,7 @@ def test_adjoint_with_moving_wall_matches_oracle():
     np.testing.assert_allclose(dF, gF, rtol=1e-10)
 
 
-@pytest.mark.parametrize("method", ["SRT", "TRT"])
+@pytest.mark.parametrize("method", ["SRT", "TRT", "MRT"])
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("T,k", [(13, 4), (12, 5), (7, 1)])
