@@ -946,12 +946,10 @@ __device__ __forceinline__ void collide_cumulant_general(R* f, const R* /*F*/, c
 // of n is dh.  The Guo source has components of orders 1 and 2 only and
 // enters as in the MRT operator, (1 - omega/2) on its shear and
 // (1 - omega_b/2) on its bulk part.
-// Reciprocal for the entropic weights 1/f^eq: the hardware approximation
-// refined by Newton steps r <- r (2 - x r) (one in FP32, two in FP64).
-__device__ __forceinline__ float recip(float x) {
-  float r = __builtin_amdgcn_rcpf(x);
-  return r * (2.0f - x * r);
-}
+// Reciprocal for the entropic weights 1/f^eq, which only set the rate
+// omega_h: in FP32 the hardware reciprocal (1 ulp); in FP64 the hardware
+// approximation refined by two Newton steps r <- r (2 - x r).
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = r * (2.0 - x * r);
@@ -960,10 +958,20 @@ __device__ __forceinline__ double recip(double x) {
 
 template <class L, class R>
 __device__ __forceinline__ void collide_kbc(R* f, const R* F, const CollideParams<R>& p) {
-  constexpr int D = L::DIM;
+  // Every quantity is split over the (q, opp q) pairs: f^eq, the order-2
+  // parts and the source's order-2 part are even in c, the order-1 parts
+  // odd, so each pair costs one evaluation of each.
+  constexpr int D = L::DIM, H = L::H;
   constexpr R cs2 = R(1.0 / 3.0);
-  R drho, jx, jy, jz;
-  density_momentum<L>(f, drho, jx, jy, jz);
+  R drho = f[0], jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    const R sp = f[q] + f[q + H], dm = f[q] - f[q + H];
+    drho += sp;
+    if (L::c(q, 0) != 0) jx += R(L::c(q, 0)) * dm;
+    if (L::c(q, 1) != 0) jy += R(L::c(q, 1)) * dm;
+    if (L::c(q, 2) != 0) jz += R(L::c(q, 2)) * dm;
+  }
   const R rho = p.rho0 + drho;
   const R rr = p.compressible ? rho : p.rho0;
   const R inv = R(1) / rr;
@@ -973,32 +981,29 @@ __device__ __forceinline__ void collide_kbc(R* f, const R* F, const CollideParam
   const R uF = ux * F[0] + uy * F[1] + uz * F[2];
   // pass 1: non-equilibrium n = f - f^eq (f^eq = f - n later) and its moments
   R n[L::Q];
+  n[0] = f[0] - R(weight<L>(0)) * (drho - rr * usq);
   R Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0, Jx = 0, Jy = 0, Jz = 0;
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
+  for (int q = 1; q <= H; ++q) {
+    const int o = q + H;
     const R w = R(weight<L>(q));
     const R cu = cdot<L>(q, ux, uy, uz);
-    n[q] = f[q] - w * (drho + rr * (R(3) * cu + R(4.5) * cu * cu - usq));   // f^eq shifted by w rho_0
+    const R E = w * (drho + rr * (R(4.5) * cu * cu - usq));   // f^eq shifted by w rho_0: E +- O
+    const R O = w * rr * R(3) * cu;
+    n[q] = f[q] - (E + O);
+    n[o] = f[o] - (E - O);
+    const R sp = n[q] + n[o], dm = n[q] - n[o];
     const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
-    if (cx != 0) Pxx += n[q];
-    if (cy != 0) Pyy += n[q];
-    if (cz != 0) Pzz += n[q];
-    if (cx * cy == 1) Pxy += n[q];
-    if (cx * cy == -1) Pxy -= n[q];
-    if (cx * cz == 1) Pxz += n[q];
-    if (cx * cz == -1) Pxz -= n[q];
-    if (cy * cz == 1) Pyz += n[q];
-    if (cy * cz == -1) Pyz -= n[q];
-    if (cx == 1) Jx += n[q];
-    if (cx == -1) Jx -= n[q];
-    if (cy == 1) Jy += n[q];
-    if (cy == -1) Jy -= n[q];
-    if (cz == 1) Jz += n[q];
-    if (cz == -1) Jz -= n[q];
+    if (cx != 0) { Pxx += sp; Jx += R(cx) * dm; }
+    if (cy != 0) { Pyy += sp; Jy += R(cy) * dm; }
+    if (cz != 0) { Pzz += sp; Jz += R(cz) * dm; }
+    if (cx * cy != 0) Pxy += R(cx * cy) * sp;
+    if (cx * cz != 0) Pxz += R(cx * cz) * sp;
+    if (cy * cz != 0) Pyz += R(cy * cz) * sp;
   }
   const R tr = Pxx + Pyy + Pzz;
   const R trD = tr * (R(1) / R(D));
-  // second-order part of n at q (Hermite projection), and its bulk part
+  // second-order part of n at q (Hermite projection, even in c), its bulk part
   auto d2_of = [&](int q) {
     const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
     R h2 = -cs2 * tr;
@@ -1016,33 +1021,51 @@ __device__ __forceinline__ void collide_kbc(R* f, const R* F, const CollideParam
   };
   // pass 2: dh (kept in n) and the entropic products
   R sh = 0, bh = 0, hh = 0;
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const R d2 = d2_of(q), db = db_of(q);
-    const R dh = n[q] - R(3 * weight<L>(q)) * cdot<L>(q, Jx, Jy, Jz) - d2;
-    const R ie = recip(R(weight<L>(q)) * p.rho0 + (f[q] - n[q]));
-    const R dhe = dh * ie;
-    sh += (d2 - db) * dhe;
+  {
+    const R d2 = d2_of(0), db = db_of(0);   // the rest population has no shear part: d2 = db
+    const R dh = n[0] - d2;
+    const R dhe = dh * recip(R(weight<L>(0)) * p.rho0 + (f[0] - n[0]));
     bh += db * dhe;
     hh += dh * dhe;
-    n[q] = dh;
+    n[0] = dh;
+  }
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    const int o = q + H;
+    const R d2 = d2_of(q), db = db_of(q);
+    const R cJ = R(3 * weight<L>(q)) * cdot<L>(q, Jx, Jy, Jz);
+    const R dq = n[q] - d2 - cJ, dp = n[o] - d2 + cJ;
+    const R eq = dq * recip(R(weight<L>(q)) * p.rho0 + (f[q] - n[q]));
+    const R ep = dp * recip(R(weight<L>(q)) * p.rho0 + (f[o] - n[o]));
+    sh += (d2 - db) * (eq + ep);
+    bh += db * (eq + ep);
+    hh += dq * eq + dp * ep;
+    n[q] = dq;
+    n[o] = dp;
   }
   const R om = p.om, omb = p.om_b;
   const R omh = hh > R(0) ? R(1) + ((R(1) - om) * sh + (R(1) - omb) * bh) / hh : R(1);
   const R fs = R(1) - R(0.5) * om, fbs = (R(1) - R(0.5) * omb) - fs;
   const R dom = om - omb;
   const R uFD = R(2) * uF * (R(1) / R(D));   // trace of the source's second moment u F + F u, over D
-  // pass 3: relax; the Guo source's order-1 part enters fully, its order-2
-  // part with (1 - omega/2) (shear) and (1 - omega_b/2) (bulk)
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const R w = R(weight<L>(q));
+  // pass 3: relax; the Guo source's order-1 part (odd) enters fully, its
+  // order-2 part (even) with (1 - omega/2) (shear) and (1 - omega_b/2) (bulk)
+  auto s2b_of = [&](int q) {
     const int cx = L::c(q, 0), cy = L::c(q, 1), cz = L::c(q, 2);
+    return R(4.5 * weight<L>(q) * ((double)(cx * cx + cy * cy + cz * cz) - D / 3.0)) * uFD;
+  };
+  f[0] = f[0] - om * d2_of(0) + dom * db_of(0) - omh * n[0] + fs * (R(-3 * weight<L>(0)) * uF) +
+         fbs * s2b_of(0);
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    const int o = q + H;
+    const R w = R(weight<L>(q));
     const R cu = cdot<L>(q, ux, uy, uz);
     const R cF = cdot<L>(q, F[0], F[1], F[2]);
-    const R s2 = w * (R(9) * cu * cF - R(3) * uF);
-    const R s2b = R(4.5 * weight<L>(q) * ((double)(cx * cx + cy * cy + cz * cz) - D / 3.0)) * uFD;
-    f[q] = f[q] - om * d2_of(q) + dom * db_of(q) - omh * n[q] + R(3) * w * cF + fs * s2 + fbs * s2b;
+    const R even = -om * d2_of(q) + dom * db_of(q) + fs * (w * (R(9) * cu * cF - R(3) * uF)) + fbs * s2b_of(q);
+    const R odd = R(3) * w * cF;
+    f[q] = f[q] + even - omh * n[q] + odd;
+    f[o] = f[o] + even - omh * n[o] - odd;
   }
 }
 
