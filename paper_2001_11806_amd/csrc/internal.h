@@ -15,7 +15,12 @@ struct Geo {
   int nxb;        // x-segments per row
   int bx;         // threads per block (multiple of 64)
   int64_t N;      // nx * ny * nz
+  int order;      // block -> row-segment order, see cell_of: bit 0 reversed, bit 1 XCD slabs
 };
+
+// Grids of at most this many bytes are swept with cached stores and the
+// cache-friendly block order; larger ones stream with non-temporal stores.
+constexpr size_t kStreamGridBytes = size_t(512) << 20;
 
 // Runtime parameters in FP64; each launcher converts to its compute type.
 struct Params {

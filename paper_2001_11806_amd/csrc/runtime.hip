@@ -155,7 +155,7 @@ int32_t validate(const lbm_config* cfg) {
 }
 
 Geo make_geo(const lbm_config& c) {
-  Geo g;
+  Geo g{};
   g.nx = c.nx;
   g.ny = c.ny;
   g.nz = c.nz;
@@ -195,9 +195,20 @@ int32_t alloc(void** p, size_t bytes, const char* what) {
   return LBM_OK;
 }
 
-int32_t sweep_once(lbm_ctx* c, const void* src, void* dst) {
-  HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, src, dst, c->flags, c->force, c->g, c->p,
-                       c->has_mask, c->stream),
+// Geometry of the sweep (or adjoint sweep) of time step t.  Grids within
+// reach of the caches use the XCD-slab block order and alternate the
+// traversal direction every step; larger grids keep the plain order (the
+// slabs and the reversal measured slower there).
+Geo sweep_geo(const lbm_ctx* c, int64_t t) {
+  Geo g = c->g;
+  if (c->grid_bytes <= kStreamGridBytes) g.order = (num_blocks(g) % 8 == 0 ? 2 : 0) | (int)(t & 1);
+  return g;
+}
+
+// Two-array sweep src -> dst of time step t.
+int32_t sweep_once(lbm_ctx* c, const void* src, void* dst, int64_t t) {
+  HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, src, dst, c->flags, c->force,
+                       sweep_geo(c, t), c->p, c->has_mask, c->stream),
           "sweep launch");
   return LBM_OK;
 }
@@ -212,10 +223,10 @@ int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
 int32_t step_once(lbm_ctx* c) {
   if (is_aa(c)) {
     HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
-                         c->force, c->g, c->p, c->has_mask, c->stream),
+                         c->force, sweep_geo(c, c->t), c->p, c->has_mask, c->stream),
             "AA sweep launch");
   } else {
-    int32_t st = sweep_once(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
+    int32_t st = sweep_once(c, c->grid[c->cur], c->grid[c->cur ^ 1], c->t);
     if (st != LBM_OK) return st;
     c->cur ^= 1;
   }
@@ -239,10 +250,10 @@ int32_t ensure_graph(lbm_ctx* c, int parity) {
   for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) {
     if (is_aa(c))   // parity = time parity: even / odd kernels alternate on one array
       e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, cur, c->grid[0], nullptr, c->flags, c->force,
-                       c->g, c->p, c->has_mask, c->cap_stream);
+                       sweep_geo(c, cur), c->p, c->has_mask, c->cap_stream);
     else            // parity = current grid
       e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, c->grid[cur], c->grid[cur ^ 1], c->flags,
-                       c->force, c->g, c->p, c->has_mask, c->cap_stream);
+                       c->force, sweep_geo(c, i), c->p, c->has_mask, c->cap_stream);
     cur ^= 1;
   }
   hipGraph_t graph = nullptr;
@@ -581,7 +592,7 @@ int32_t forward_state(lbm_ctx* c, int64_t s, const void** out) {
     const void* src = slot;
     for (int64_t i = 1; i <= last; ++i) {
       void* dst = (char*)c->seg + (size_t)(i - 1) * c->grid_bytes;
-      int32_t st = sweep_once(c, src, dst);
+      int32_t st = sweep_once(c, src, dst, j * c->k + i - 1);
       if (st != LBM_OK) return st;
       src = dst;
     }
@@ -605,7 +616,8 @@ int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n) {
     if (st != LBM_OK) return st;
     // transpose of the AA even (s even) or odd kernel, in place on lambda
     HIP_TRY(launch_adjoint_sweep(ctx->cfg.stencil, ctx->kmethod, ctx->cfg.dtype, (int)(s & 1), P, ctx->flags,
-                                 ctx->has_mask, ctx->force, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
+                                 ctx->has_mask, ctx->force, ctx->lam, ctx->adj_acc, sweep_geo(ctx, s), ctx->p,
+                                 ctx->stream),
             "adjoint sweep launch");
     ctx->adj_t -= 1;
   }

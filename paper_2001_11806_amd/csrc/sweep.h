@@ -47,7 +47,14 @@ inline CollideParams<R> to_collide_params(const Params& p) {
   return c;
 }
 
-// Thread -> cell mapping shared by all per-cell kernels.
+// Thread -> cell mapping shared by all per-cell kernels.  The hardware
+// hands out the blocks of a launch in index order, block b to XCD b mod 8.
+// Geo::order bit 1 renumbers them so that XCD k walks the k-th contiguous
+// eighth of the row segments (the rows a pull shares then meet in one L2);
+// bit 0 walks the segments from last to first.  Alternating the direction
+// every step makes a step start on the rows the previous one wrote last,
+// which are still in the Infinity Cache when the grid is not much larger
+// than it.  Set only when gridDim.x is a multiple of 8 (bit 1).
 struct CellIdx {
   int x, y, z, cell;
   bool valid;
@@ -55,8 +62,11 @@ struct CellIdx {
 
 __device__ __forceinline__ CellIdx cell_of(const Geo& g) {
   CellIdx c;
-  const int seg = blockIdx.x % g.nxb;
-  const int row = blockIdx.x / g.nxb;
+  unsigned b = blockIdx.x;
+  if (g.order & 2) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+  if (g.order & 1) b = gridDim.x - 1u - b;
+  const int seg = b % g.nxb;
+  const int row = b / g.nxb;
   c.x = seg * g.bx + threadIdx.x;
   c.y = row % g.ny;
   c.z = row / g.ny;
@@ -354,7 +364,7 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
   using R = typename Storage<T>::R;
   const CollideParams<R> cp = to_collide_params<R>(p);
   // non-temporal stores once the grid clearly exceeds the on-chip caches
-  const bool nt = (size_t)g.N * L::Q * sizeof(T) > (size_t(512) << 20);
+  const bool nt = (size_t)g.N * L::Q * sizeof(T) > kStreamGridBytes;
   const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
   if (phase < 0) {
     if (nt)
