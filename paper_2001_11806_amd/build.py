@@ -25,6 +25,11 @@ FLAGS = [
     # the weighted Gram-Schmidt MRT basis of D3Q27 is built at compile time
     # and needs more constant-evaluation steps than the default
     "-fconstexpr-steps=33554432",
+    # fuse a*b+c into an FMA only inside one source expression, so every
+    # kernel that inlines the same collision code rounds it the same way
+    # (the two-array and AA sweeps then agree bit for bit) whatever code
+    # surrounds it
+    "-ffp-contract=on",
 ]
 
 
