@@ -36,8 +36,10 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the kernel sources and the build flags (build.py)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2001_11806_amd", "csrc", "*"))):
+    pkg = os.path.join(ROOT, "paper_2001_11806_amd")
+    for f in sorted(glob.glob(os.path.join(pkg, "csrc", "*"))) + [os.path.join(pkg, "build.py")]:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
