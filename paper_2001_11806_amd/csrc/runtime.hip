@@ -195,13 +195,21 @@ int32_t alloc(void** p, size_t bytes, const char* what) {
   return LBM_OK;
 }
 
+bool is_aa(const lbm_ctx* c) { return c->cfg.pattern == 1; }
+
 // Geometry of the sweep (or adjoint sweep) of time step t.  Grids within
 // reach of the caches use the XCD-slab block order and alternate the
-// traversal direction every step; larger grids keep the plain order (the
-// slabs and the reversal measured slower there).
-Geo sweep_geo(const lbm_ctx* c, int64_t t) {
+// traversal direction every step.  Larger grids keep the plain order (the
+// slabs and the reversal measured slower there), except the forward AA
+// kernels (aa_forward), which update one array in place: alternating the
+// direction makes each step start on the rows the previous step wrote last
+// (measured 2-4 % faster on 256^3).
+Geo sweep_geo(const lbm_ctx* c, int64_t t, bool aa_forward = false) {
   Geo g = c->g;
-  if (c->grid_bytes <= kStreamGridBytes) g.order = (num_blocks(g) % 8 == 0 ? 2 : 0) | (int)(t & 1);
+  if (c->grid_bytes <= kStreamGridBytes)
+    g.order = (num_blocks(g) % 8 == 0 ? 2 : 0) | (int)(t & 1);
+  else if (aa_forward)
+    g.order = (int)(t & 1);
   return g;
 }
 
@@ -213,7 +221,6 @@ int32_t sweep_once(lbm_ctx* c, const void* src, void* dst, int64_t t) {
   return LBM_OK;
 }
 
-bool is_aa(const lbm_ctx* c) { return c->cfg.pattern == 1; }
 
 // Layout of the stored state (see aux.hip): two arrays 0; AA 2 after an even
 // number of steps (streamed), 1 after an odd number (inverted).
@@ -223,7 +230,7 @@ int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
 int32_t step_once(lbm_ctx* c) {
   if (is_aa(c)) {
     HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
-                         c->force, sweep_geo(c, c->t), c->p, c->has_mask, c->stream),
+                         c->force, sweep_geo(c, c->t, true), c->p, c->has_mask, c->stream),
             "AA sweep launch");
   } else {
     int32_t st = sweep_once(c, c->grid[c->cur], c->grid[c->cur ^ 1], c->t);
@@ -250,7 +257,7 @@ int32_t ensure_graph(lbm_ctx* c, int parity) {
   for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) {
     if (is_aa(c))   // parity = time parity: even / odd kernels alternate on one array
       e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, cur, c->grid[0], nullptr, c->flags, c->force,
-                       sweep_geo(c, cur), c->p, c->has_mask, c->cap_stream);
+                       sweep_geo(c, cur, true), c->p, c->has_mask, c->cap_stream);
     else            // parity = current grid
       e = launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, c->grid[cur], c->grid[cur ^ 1], c->flags,
                        c->force, sweep_geo(c, i), c->p, c->has_mask, c->cap_stream);
