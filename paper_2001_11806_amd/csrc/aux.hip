@@ -4,6 +4,8 @@
 //
 // These run once per run or once per readout, not per time step, so they
 // compute in FP64 regardless of the storage type.
+#include <algorithm>
+
 #include "sweep.h"
 
 namespace lbm {
@@ -383,16 +385,36 @@ __global__ __launch_bounds__(256) void k_copy_generic(const E* __restrict__ src,
   for (int q = 0; q < Q; ++q) dst[q * n + i] = src[q * n + i];
 }
 
+// The copy reference runs in the launch shape of the sweeps: 8-byte
+// elements on streaming sizes at 12 waves per CU, like the FP64 sweep.
 template <class E>
 hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const unsigned lds =
+      (sizeof(E) == 8 && (size_t)n * (size_t)q * sizeof(E) > kStreamGridBytes) ? occupancy_lds(12, 256) : 0u;
   switch (q) {
-    case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
-    case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
-    case 27: hipLaunchKernelGGL((k_copy_q<E, 27>), grid, block, 0, s, (const E*)src, (E*)dst, n); break;
-    default: hipLaunchKernelGGL((k_copy_generic<E>), grid, block, 0, s, (const E*)src, (E*)dst, n, q);
+    case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    case 27: hipLaunchKernelGGL((k_copy_q<E, 27>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    default: hipLaunchKernelGGL((k_copy_generic<E>), grid, block, lds, s, (const E*)src, (E*)dst, n, q);
   }
   return hipGetLastError();
+}
+
+unsigned occupancy_lds(int waves_per_cu, int block_threads) {
+  static int lds_per_cu[64];   // LDS bytes per CU of each device, queried once
+  int dev = 0;
+  if (waves_per_cu <= 0 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0u;
+  if (lds_per_cu[dev] <= 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || v <= 0)
+      return 0u;
+    lds_per_cu[dev] = v;
+  }
+  const int blocks = waves_per_cu / ((block_threads + 63) / 64);   // resident blocks per CU wanted
+  if (blocks < 2) return 0u;
+  const int lds = std::min(65536, lds_per_cu[dev] / blocks);
+  return lds_per_cu[dev] / lds == blocks ? (unsigned)lds : 0u;
 }
 
 hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, hipStream_t s) {

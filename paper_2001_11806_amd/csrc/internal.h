@@ -22,6 +22,13 @@ struct Geo {
 // cache-friendly block order; larger ones stream with non-temporal stores.
 constexpr size_t kStreamGridBytes = size_t(512) << 20;
 
+// Dynamic LDS bytes to request (and leave unused) so that at most
+// `waves_per_cu` wavefronts of blocks of `block_threads` threads share a CU;
+// 0 (no limit) when the request cannot express that.  A streaming kernel at
+// full occupancy keeps more loads in flight than HBM needs, and fewer
+// resident waves measured faster for some of them.
+unsigned occupancy_lds(int waves_per_cu, int block_threads);
+
 // Runtime parameters in FP64; each launcher converts to its compute type.
 struct Params {
   double rho0;

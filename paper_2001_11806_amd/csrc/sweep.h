@@ -178,13 +178,23 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
-  int fl = 0;
-  if (has_mask) {
-    fl = flags[c.cell];
-    if (fl & 1) return;  // solid cells are never updated
-  }
   R f[L::Q];
-  gather<L, T>(src, flags, fl, c, g, f, nullptr, p);
+  int fl = 0;
+  if (NT) {
+    // streaming grids: issue the Q loads together with the flag byte instead
+    // of after it, so a wave does not wait one memory round trip before its
+    // loads start (the launch runs fewer waves per CU, see run_sweep); a
+    // solid cell's loads are then wasted, in bounds
+    if (has_mask) fl = flags[c.cell];
+    gather<L, T>(src, flags, fl, c, g, f, nullptr, p);
+    if (fl & 1) return;  // solid cells are never updated
+  } else {
+    if (has_mask) {
+      fl = flags[c.cell];
+      if (fl & 1) return;  // solid cells are never updated
+    }
+    gather<L, T>(src, flags, fl, c, g, f, nullptr, p);
+  }
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
   store_cell<T, NT>(dst, c, g, f, L::Q);
@@ -367,9 +377,14 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
   const bool nt = (size_t)g.N * L::Q * sizeof(T) > kStreamGridBytes;
   const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
   if (phase < 0) {
+    // FP64 two-array sweeps of the light operators on streaming grids run 12
+    // waves per CU (measured fastest, 256^3 channel); the others need full
+    // occupancy or were not faster
+    const unsigned lds = (nt && sizeof(T) == 8 && (M == M_SRT || M == M_TRT || M == M_MRT))
+                             ? occupancy_lds(12, g.bx) : 0u;
     if (nt)
-      hipLaunchKernelGGL((k_sweep<L, M, T, 1>), grid, block, 0, s, (const T*)src, (T*)dst, flags, (const R*)force_y,
-                         g, cp, has_mask);
+      hipLaunchKernelGGL((k_sweep<L, M, T, 1>), grid, block, lds, s, (const T*)src, (T*)dst, flags,
+                         (const R*)force_y, g, cp, has_mask);
     else
       hipLaunchKernelGGL((k_sweep<L, M, T, 0>), grid, block, 0, s, (const T*)src, (T*)dst, flags, (const R*)force_y,
                          g, cp, has_mask);
