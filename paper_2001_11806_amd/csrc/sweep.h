@@ -377,10 +377,11 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
   const bool nt = (size_t)g.N * L::Q * sizeof(T) > kStreamGridBytes;
   const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
   if (phase < 0) {
-    // FP64 two-array sweeps of the light operators on streaming grids run 12
-    // waves per CU (measured fastest, 256^3 channel); the others need full
-    // occupancy or were not faster
-    const unsigned lds = (nt && sizeof(T) == 8 && (M == M_SRT || M == M_TRT || M == M_MRT))
+    // FP64 two-array sweeps of the SRT / TRT / MRT / unit-rate cumulant
+    // operators on streaming grids run 12 waves per CU (measured fastest:
+    // 256^3 channel, 384^3 cumulant); the others need full occupancy or were
+    // not faster
+    const unsigned lds = (nt && sizeof(T) == 8 && (M == M_SRT || M == M_TRT || M == M_MRT || M == M_CUMULANT))
                              ? occupancy_lds(12, g.bx) : 0u;
     if (nt)
       hipLaunchKernelGGL((k_sweep<L, M, T, 1>), grid, block, lds, s, (const T*)src, (T*)dst, flags,
