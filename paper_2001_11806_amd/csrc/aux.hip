@@ -385,13 +385,14 @@ __global__ __launch_bounds__(256) void k_copy_generic(const E* __restrict__ src,
   for (int q = 0; q < Q; ++q) dst[q * n + i] = src[q * n + i];
 }
 
-// The copy reference runs in the launch shape of the sweeps: 8-byte
-// elements on streaming sizes at 12 waves per CU, like the FP64 sweep.
+// The copy reference runs in the launch shape of the D3Q19 sweeps on
+// streaming sizes: 12 waves per CU for 8-byte elements, 16 for 4-byte
+// elements, full occupancy for 2-byte elements.
 template <class E>
 hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const unsigned lds =
-      (sizeof(E) == 8 && (size_t)n * (size_t)q * sizeof(E) > kStreamGridBytes) ? occupancy_lds(12, 256) : 0u;
+  const bool stream = (size_t)n * (size_t)q * sizeof(E) > kStreamGridBytes;
+  const unsigned lds = !stream ? 0u : occupancy_lds(sizeof(E) == 8 ? 12 : (sizeof(E) == 4 ? 16 : 0), 256);
   switch (q) {
     case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
     case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;

@@ -377,12 +377,17 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
   const bool nt = (size_t)g.N * L::Q * sizeof(T) > kStreamGridBytes;
   const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
   if (phase < 0) {
-    // FP64 two-array sweeps of the SRT / TRT / MRT / unit-rate cumulant
-    // operators on streaming grids run 12 waves per CU (measured fastest:
-    // 256^3 channel, 384^3 cumulant); the others need full occupancy or were
-    // not faster
-    const unsigned lds = (nt && sizeof(T) == 8 && (M == M_SRT || M == M_TRT || M == M_MRT || M == M_CUMULANT))
-                             ? occupancy_lds(12, g.bx) : 0u;
+    // Waves per CU of the two-array sweep on streaming grids, measured per
+    // storage type and operator (256^3 and 384^3 lattices): 12 for FP64
+    // SRT / TRT / MRT / unit-rate cumulant; FP32 SRT / TRT 16 on D3Q19 and
+    // 12 on D3Q27; full occupancy for the rest (16-bit, FP32 MRT, which lost
+    // 7 % at 12, FP32 cumulant, KBC, Smagorinsky)
+    constexpr bool srt_trt = M == M_SRT || M == M_TRT;
+    const int waves = !nt ? 0
+                      : sizeof(T) == 8 ? ((srt_trt || M == M_MRT || M == M_CUMULANT) ? 12 : 0)
+                      : sizeof(T) == 4 ? (srt_trt ? (L::Q == 19 ? 16 : 12) : 0)
+                                       : 0;
+    const unsigned lds = occupancy_lds(waves, g.bx);
     if (nt)
       hipLaunchKernelGGL((k_sweep<L, M, T, 1>), grid, block, lds, s, (const T*)src, (T*)dst, flags,
                          (const R*)force_y, g, cp, has_mask);
