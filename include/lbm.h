@@ -157,7 +157,8 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
  * AA even and odd kernels alternating with pattern 1; with launch_mode 0
  * small lattices replay a captured graph of 32 launches).  With the tape
  * enabled, the state at every multiple of k steps below max_tape_steps is
- * copied into the tape first (in the two-array layout). */
+ * kept in the tape, in the two-array layout (the two-array sweep writes it
+ * there directly; with AA it is copied out of the single array). */
 int32_t lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Readout of the stored (post-collision) state: rho = sum f,

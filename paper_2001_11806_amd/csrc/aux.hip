@@ -287,14 +287,20 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
 
 // --------------------------------------------------------------- PDF I/O
 template <class L, class T>
-__global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                  int has_mask, int layout, double* __restrict__ out, Geo g,
-                                                  double rho0, const typename Storage<T>::R* wall) {
+__global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const T* __restrict__ P_solid,
+                                                  const uint8_t* __restrict__ flags, int has_mask, int layout,
+                                                  double* __restrict__ out, Geo g, double rho0,
+                                                  const typename Storage<T>::R* wall) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double v[L::Q];
-  load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+  if (has_mask && (flags[c.cell] & 1)) {   // solid cells keep their own slots in every layout
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P_solid + q * N + c.cell);
+  } else {
+    load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+  }
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) out[q * N + c.cell] = v[q] + weight<L>(q) * rho0;
 }
@@ -312,12 +318,13 @@ __global__ __launch_bounds__(512) void k_set_pdfs(T* P, const uint8_t* __restric
   store_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
 }
 
-hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask, int layout,
-                           double* out, const Geo& g, const Params& p, hipStream_t s) {
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const void* P_solid, const uint8_t* flags,
+                           int has_mask, int layout, double* out, const Geo& g, const Params& p, hipStream_t s) {
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
-      hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, layout, out, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+      hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P,
+                         (const T*)P_solid, flags, has_mask, layout, out, g, p.rho0,
+                         (const typename Storage<T>::R*)p.wall);
       return hipGetLastError();
     })
   })

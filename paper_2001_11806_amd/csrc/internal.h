@@ -65,8 +65,9 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
 hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags,
                             int has_mask, int layout, double* partials, double* out4, const Geo& g,
                             const Params& p, hipStream_t s);
-hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
-                           int layout, double* out, const Geo& g, const Params& p, hipStream_t s);
+// Solid cells are read from P_solid (the buffer that keeps their values).
+hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const void* P_solid, const uint8_t* flags,
+                           int has_mask, int layout, double* out, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
                            const double* in, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,

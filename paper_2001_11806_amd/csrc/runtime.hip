@@ -48,7 +48,10 @@ struct lbm_ctx {
   hipStream_t stream = nullptr;
   size_t grid_bytes = 0;
   void* grid[2] = {nullptr, nullptr};
-  int cur = 0;
+  // Buffer holding the current state: grid[0] with AA; with two arrays one
+  // of the grids, or a tape slot while a tape is recorded.  Solid cells keep
+  // their values in the grids only (the sweep never writes them).
+  void* state = nullptr;
   uint8_t* flags = nullptr;
   uint32_t* links = nullptr;   // bounced-link bits per cell (with a mask)
   int has_mask = 0;
@@ -213,6 +216,20 @@ Geo sweep_geo(const lbm_ctx* c, int64_t t, bool aa_forward = false) {
   return g;
 }
 
+char* tape_slot(const lbm_ctx* c, int64_t j) { return (char*)c->tape + (size_t)j * c->grid_bytes; }
+
+// Where the two-array sweep stores the state of time s: a checkpoint of the
+// tape (s a multiple of k below max_tape_steps) straight into its tape slot,
+// which saves the copy; any other state into the grid that does not hold the
+// source.  (Keeping every state of the running segment in the segment
+// buffer as well, to skip its recompute, made the forward slower by as much
+// as the backward gained.)  nullptr if the slot index is out of range.
+void* place(const lbm_ctx* c, int64_t s, const void* src) {
+  if (c->k > 0 && s < c->cfg.max_tape_steps && s % c->k == 0)
+    return s / c->k < c->nslots ? tape_slot(c, s / c->k) : nullptr;
+  return src == c->grid[0] ? c->grid[1] : c->grid[0];
+}
+
 // Two-array sweep src -> dst of time step t.
 int32_t sweep_once(lbm_ctx* c, const void* src, void* dst, int64_t t) {
   HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, -1, src, dst, c->flags, c->force,
@@ -233,9 +250,12 @@ int32_t step_once(lbm_ctx* c) {
                          c->force, sweep_geo(c, c->t, true), c->p, c->has_mask, c->stream),
             "AA sweep launch");
   } else {
-    int32_t st = sweep_once(c, c->grid[c->cur], c->grid[c->cur ^ 1], c->t);
+    void* dst = place(c, c->t + 1, c->state);
+    if (!dst || dst == c->state) return fail(LBM_EHIP, "internal: no buffer for the state of step %lld",
+                                             (long long)(c->t + 1));
+    int32_t st = sweep_once(c, c->state, dst, c->t);
     if (st != LBM_OK) return st;
-    c->cur ^= 1;
+    c->state = dst;
   }
   c->t += 1;
   return LBM_OK;
@@ -340,6 +360,7 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   };
   for (int i = 0; i < (cfg->pattern == 1 ? 1 : 2); ++i)
     if ((st = alloc(&c->grid[i], c->grid_bytes, "PDF grid")) != LBM_OK) return bail(st);
+  c->state = c->grid[0];
   if ((st = alloc(&c->force, 3 * (size_t)cfg->ny * rb, "force table")) != LBM_OK) return bail(st);
   if ((st = alloc(&c->wall, 3 * 128 * rb, "wall velocity table")) != LBM_OK) return bail(st);
   c->p.wall = c->wall;
@@ -459,7 +480,7 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
   if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
   int32_t st = check_field_dtype(field_dtype);
   if (st != LBM_OK) return st;
-  ctx->cur = 0;
+  ctx->state = ctx->grid[0];
   ctx->t = 0;
   HIP_TRY(launch_init(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, layout_of(ctx),
                       rho_dev, u_dev, field_dtype, ctx->g, ctx->p, ctx->stream),
@@ -480,7 +501,7 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
   int32_t i = 0;
   if (graph_replay(ctx)) {
     for (; n - i >= kGraphSteps; i += kGraphSteps) {
-      const int key = is_aa(ctx) ? (int)(ctx->t & 1) : ctx->cur;
+      const int key = is_aa(ctx) ? (int)(ctx->t & 1) : (ctx->state == ctx->grid[0] ? 0 : 1);
       int32_t st = ensure_graph(ctx, key);
       if (st != LBM_OK) return st;
       HIP_TRY(hipGraphLaunch(ctx->graph_exec[key], ctx->stream), "graph launch");
@@ -491,13 +512,13 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
     if (ctx->k > 0 && ctx->t < ctx->cfg.max_tape_steps && ctx->t % ctx->k == 0) {
       // the tape holds two-array layout: the segment recompute and the
       // adjoint gather read it with the two-array kernels
-      char* slot = (char*)ctx->tape + (size_t)(ctx->t / ctx->k) * ctx->grid_bytes;
+      char* slot = tape_slot(ctx, ctx->t / ctx->k);
       if (is_aa(ctx))
         HIP_TRY(launch_relayout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask,
                                 layout_of(ctx), slot, ctx->g, ctx->p, ctx->stream),
                 "tape relayout");
-      else
-        HIP_TRY(hipMemcpyAsync(slot, ctx->grid[ctx->cur], ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
+      else if (ctx->state != slot)   // the initial state; later checkpoints are swept into their slots
+        HIP_TRY(hipMemcpyAsync(slot, ctx->state, ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
                 "tape copy");
     }
     int32_t st = step_once(ctx);
@@ -518,7 +539,7 @@ int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t fi
   int32_t st = check_field_dtype(field_dtype);
   if (st != LBM_OK) return st;
   if (!rho_dev && !u_dev) return LBM_OK;
-  HIP_TRY(launch_readout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+  HIP_TRY(launch_readout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->state, ctx->flags, ctx->has_mask,
                          layout_of(ctx), ctx->force,
                          rho_dev, u_dev, field_dtype, ctx->g, ctx->p, ctx->stream),
           "readout launch");
@@ -527,7 +548,7 @@ int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t fi
 
 int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
   if (!ctx || !out) return fail(LBM_EINVAL, "NULL argument");
-  HIP_TRY(launch_conserved(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+  HIP_TRY(launch_conserved(ctx->cfg.stencil, ctx->cfg.dtype, ctx->state, ctx->flags, ctx->has_mask,
                            layout_of(ctx), ctx->partials, ctx->acc + 4, ctx->g, ctx->p, ctx->stream),
           "conservation launch");
   HIP_TRY(hipMemcpyAsync(out, ctx->acc + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "totals copy");
@@ -539,7 +560,8 @@ int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
 
 int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev) {
   if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
-  HIP_TRY(launch_get_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+  // solid cells are reported from grid[0], which alone keeps their values
+  HIP_TRY(launch_get_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->state, ctx->grid[0], ctx->flags, ctx->has_mask,
                           layout_of(ctx), pdfs_dev, ctx->g, ctx->p, ctx->stream),
           "get_pdfs launch");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "get_pdfs sync");
@@ -549,7 +571,7 @@ int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev) {
 int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev) {
   if (!ctx || !pdfs_dev) return fail(LBM_EINVAL, "NULL argument");
   if (ctx->k > 0) return fail(LBM_ESTATE, "set_pdfs is not available with the adjoint tape (no initial fields)");
-  ctx->cur = 0;
+  ctx->state = ctx->grid[0];
   ctx->t = 0;
   HIP_TRY(launch_set_pdfs(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask, layout_of(ctx),
                           pdfs_dev, ctx->g, ctx->p, ctx->stream),
@@ -573,7 +595,7 @@ int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_d
   // lambda^T goes into the AA layout of time T (1 after an odd number of
   // steps, 2 after an even one) whatever the forward pattern; the seed
   // writes every slot
-  HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[ctx->cur], ctx->flags, ctx->has_mask,
+  HIP_TRY(launch_adjoint_seed(ctx->cfg.stencil, ctx->cfg.dtype, ctx->state, ctx->flags, ctx->has_mask,
                               layout_of(ctx), (ctx->t & 1) ? 1 : 2, ctx->force, dL_drho_dev, dL_du_dev,
                               field_dtype, ctx->lam, ctx->adj_acc, ctx->g, ctx->p, ctx->stream),
           "adjoint seed launch");

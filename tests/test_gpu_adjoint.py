@@ -228,3 +228,75 @@ def test_adjoint_in_xcd_slab_order_matches_oracle(method, pattern):
     assert rel_l2(du, gu) <= 1e-10
     assert rel_l2(drho, grho) <= 1e-10
     np.testing.assert_allclose(dF, gF, rtol=1e-10)
+
+
+def _tape_ctx(dims, mask, k, T, pattern=0, dtype="f64"):
+    g = make_gpu("D3Q19", "SRT", dtype, dims, mask, RATES, checkpoint_every=k, max_tape_steps=T, pattern=pattern)
+    return g
+
+
+def _seeded_grads(g, mask):
+    _, u_T = g.macroscopic()
+    dL = torch.zeros_like(u_T)
+    fl = torch.tensor(mask == 0, device=u_T.device)
+    dL[0, :, :, -1] = 2 * u_T[0, :, :, -1] * fl[:, :, -1]
+    g.adjoint_seed(dL)
+    g.adjoint_step(g.time)
+    return g.adjoint_grads(want_rho=True)
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+def test_state_survives_the_adjoint_and_the_forward_continues(pattern):
+    """With a tape the two-array sweep writes each checkpoint straight into
+    its tape slot, so the current state may live there (T = 16) or in a grid
+    (T = 13); the adjoint must not disturb it: readout and PDFs are unchanged
+    after a full adjoint pass, and further steps match a run without a tape
+    bit for bit, solid cells included (they are kept in the grids only)."""
+    need_gpu()
+    dims = (70, 10, 6)
+    mask, rho, u0, F, _ = _case("D3Q19", dims)
+    ref = make_gpu("D3Q19", "SRT", "f64", dims, mask, RATES, pattern=pattern)
+    ref.set_force(F)
+    ref.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+    g = _tape_ctx(dims, mask, 4, 40, pattern)
+    g.set_force(F)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+    for T in (13, 16):   # the state in a grid, then in a tape slot
+        g.step(T - g.time)
+        ref.step(T - ref.time)
+        before = g.get_pdfs()
+        assert torch.equal(before, ref.get_pdfs()), T
+        _seeded_grads(g, mask)
+        assert torch.equal(g.get_pdfs(), before), T
+        (ra, ua), (rb, ub) = g.macroscopic(), ref.macroscopic()
+        assert torch.equal(ua, ub) and torch.equal(ra, rb), T
+    g.step(7)
+    ref.step(7)
+    assert torch.equal(g.get_pdfs(), ref.get_pdfs())
+    g.close()
+    ref.close()
+
+
+def test_seed_again_after_continuing_within_a_segment():
+    """T = 13, adjoint, two more steps (still in the same segment of k = 4),
+    seed again: the second pass recomputes from the same tape and its
+    gradients equal those of a fresh 15-step run bit for bit."""
+    need_gpu()
+    dims = (70, 10, 6)
+    mask, rho, u0, F, _ = _case("D3Q19", dims)
+    a = _tape_ctx(dims, mask, 4, 20)
+    a.set_force(F)
+    a.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+    a.step(13)
+    _seeded_grads(a, mask)
+    a.step(2)
+    ga = _seeded_grads(a, mask)
+    b = _tape_ctx(dims, mask, 4, 20)
+    b.set_force(F)
+    b.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+    b.step(15)
+    gb = _seeded_grads(b, mask)
+    assert torch.equal(ga[0], gb[0]) and torch.equal(ga[1], gb[1])
+    assert np.array_equal(np.asarray(ga[2]), np.asarray(gb[2]))
+    a.close()
+    b.close()
