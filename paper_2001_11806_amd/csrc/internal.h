@@ -44,7 +44,8 @@ struct Params {
 inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
 
 // forward
-// phase -1: two-array sweep src -> dst; 0 / 1: AA even / odd kernel in place on src
+// phase -1: two-array sweep src -> dst; 0 / 1: AA even / odd kernel in place on src,
+// with dst (if not null) receiving the produced state in the two-array layout
 hipError_t launch_sweep(int stencil, int method, int dtype, int phase, const void* src, void* dst,
                         const uint8_t* flags, const void* force_y, const Geo& g, const Params& p,
                         int has_mask, hipStream_t s);

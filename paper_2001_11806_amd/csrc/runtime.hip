@@ -67,6 +67,7 @@ struct lbm_ctx {
   void* tape = nullptr;        // nslots grids: P^0, P^k, ...
   void* seg = nullptr;         // k - 1 grids: recomputed states of one segment
   int64_t seg_id = -1;
+  int64_t taped_t = -1;        // AA: time of the last state written to the tape by its sweep
   bool tape_ok = false;
   void* init_fields = nullptr; // compute type: rho, ux, uy, uz
   void* lam = nullptr;         // compute type, Q * N: lambda in the AA layout of its time
@@ -246,9 +247,14 @@ int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
 // One forward step on the context's stream.
 int32_t step_once(lbm_ctx* c) {
   if (is_aa(c)) {
-    HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], nullptr, c->flags,
+    // the sweep that produces a checkpoint also writes it into its tape slot
+    const int64_t s = c->t + 1;
+    void* tape = (c->k > 0 && s < c->cfg.max_tape_steps && s % c->k == 0 && s / c->k < c->nslots)
+                     ? (void*)tape_slot(c, s / c->k) : nullptr;
+    HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], tape, c->flags,
                          c->force, sweep_geo(c, c->t, true), c->p, c->has_mask, c->stream),
             "AA sweep launch");
+    if (tape) c->taped_t = s;
   } else {
     void* dst = place(c, c->t + 1, c->state);
     if (!dst || dst == c->state) return fail(LBM_EHIP, "internal: no buffer for the state of step %lld",
@@ -310,6 +316,7 @@ int32_t mirror_grid(lbm_ctx* c) {
 void reset_time(lbm_ctx* c) {
   c->t = 0;
   c->seg_id = -1;
+  c->taped_t = -1;
   c->tape_ok = c->k > 0;
   c->adj_t = -1;
   c->adj_T = -1;
@@ -513,11 +520,12 @@ int32_t lbm_step(lbm_ctx* ctx, int32_t n) {
       // the tape holds two-array layout: the segment recompute and the
       // adjoint gather read it with the two-array kernels
       char* slot = tape_slot(ctx, ctx->t / ctx->k);
-      if (is_aa(ctx))
-        HIP_TRY(launch_relayout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask,
-                                layout_of(ctx), slot, ctx->g, ctx->p, ctx->stream),
-                "tape relayout");
-      else if (ctx->state != slot)   // the initial state; later checkpoints are swept into their slots
+      if (is_aa(ctx)) {
+        if (ctx->taped_t != ctx->t)   // the initial state; later checkpoints are written by their sweeps
+          HIP_TRY(launch_relayout(ctx->cfg.stencil, ctx->cfg.dtype, ctx->grid[0], ctx->flags, ctx->has_mask,
+                                  layout_of(ctx), slot, ctx->g, ctx->p, ctx->stream),
+                  "tape relayout");
+      } else if (ctx->state != slot)   // the initial state; later checkpoints are swept into their slots
         HIP_TRY(hipMemcpyAsync(slot, ctx->state, ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
                 "tape copy");
     }

@@ -227,10 +227,23 @@ __device__ __forceinline__ void put(T* p, typename Storage<T>::R v) {
     Storage<T>::store(p, v);
 }
 
+// Checkpoint of the AA pattern: the post-collision populations of the cell
+// in the two-array layout, slot (x, q), written by the step that produces
+// them (non-temporal: the tape is read only by the adjoint).
+template <class L, class T>
+__device__ __forceinline__ void tape_store(T* tape, const CellIdx& c, const Geo& g,
+                                           const typename Storage<T>::R* f) {
+  T* row = tape + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+  const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) Storage<T>::store_nt(at_bytes(row + (size_t)q * (size_t)g.N, ox), f[q]);
+}
+
 template <class L, int M, class T, int NT>
 __global__ __launch_bounds__(512) void k_sweep_aa_even(T* A, const uint8_t* __restrict__ flags,
                                                        const typename Storage<T>::R* __restrict__ force_y, Geo g,
-                                                       CollideParams<typename Storage<T>::R> p, int has_mask) {
+                                                       CollideParams<typename Storage<T>::R> p, int has_mask,
+                                                       T* __restrict__ tape) {
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
@@ -244,12 +257,14 @@ __global__ __launch_bounds__(512) void k_sweep_aa_even(T* A, const uint8_t* __re
   collide<L, M>(f, F, p);
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) put<T, NT>(at_bytes(row + (size_t)opp<L>(q) * (size_t)g.N, ox), f[q]);
+  if (tape) tape_store<L, T>(tape, c, g, f);
 }
 
 template <class L, int M, class T, int NT>
 __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __restrict__ flags,
                                                       const typename Storage<T>::R* __restrict__ force_y, Geo g,
-                                                      CollideParams<typename Storage<T>::R> p, int has_mask) {
+                                                      CollideParams<typename Storage<T>::R> p, int has_mask,
+                                                      T* __restrict__ tape) {
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
@@ -279,6 +294,7 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
   }
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
+  if (tape) tape_store<L, T>(tape, c, g, f);
   if (!(fl & 2)) {
 #pragma unroll
     for (int q = 0; q < L::Q; ++q)
@@ -367,7 +383,9 @@ __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_m
   }
 }
 
-// phase -1: two-array sweep src -> dst; phase 0 / 1: AA even / odd kernel on src.
+// phase -1: two-array sweep src -> dst; phase 0 / 1: AA even / odd kernel on
+// src, and dst (if not null) receives the produced state in the two-array
+// layout (a checkpoint of the tape).
 template <class L, int M, class T>
 hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags, const void* force_y, const Geo& g,
                      const Params& p, int has_mask, hipStream_t s) {
@@ -397,17 +415,17 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
   } else if (phase == 0) {
     if (nt)
       hipLaunchKernelGGL((k_sweep_aa_even<L, M, T, 1>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
-                         has_mask);
+                         has_mask, (T*)dst);
     else
       hipLaunchKernelGGL((k_sweep_aa_even<L, M, T, 0>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
-                         has_mask);
+                         has_mask, (T*)dst);
   } else {
     if (nt)
       hipLaunchKernelGGL((k_sweep_aa_odd<L, M, T, 1>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
-                         has_mask);
+                         has_mask, (T*)dst);
     else
       hipLaunchKernelGGL((k_sweep_aa_odd<L, M, T, 0>), grid, block, 0, s, (T*)src, flags, (const R*)force_y, g, cp,
-                         has_mask);
+                         has_mask, (T*)dst);
   }
   return hipGetLastError();
 }
