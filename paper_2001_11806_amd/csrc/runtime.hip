@@ -67,6 +67,7 @@ struct lbm_ctx {
   void* tape = nullptr;        // nslots grids: P^0, P^k, ...
   void* seg = nullptr;         // k - 1 grids: recomputed states of one segment
   int64_t seg_id = -1;
+  int64_t seg_fwd_lo = INT64_MAX;  // the forward wrote the last segment's states from this time on
   int64_t taped_t = -1;        // AA: time of the last state written to the tape by its sweep
   bool tape_ok = false;
   void* init_fields = nullptr; // compute type: rho, ux, uy, uz
@@ -218,16 +219,30 @@ Geo sweep_geo(const lbm_ctx* c, int64_t t, bool aa_forward = false) {
 }
 
 char* tape_slot(const lbm_ctx* c, int64_t j) { return (char*)c->tape + (size_t)j * c->grid_bytes; }
+char* seg_slot(const lbm_ctx* c, int64_t i) { return (char*)c->seg + (size_t)i * c->grid_bytes; }
+bool in_seg(const lbm_ctx* c, const void* p) {
+  return c->seg && p >= c->seg && (const char*)p < seg_slot(c, c->k - 1);
+}
 
-// Where the two-array sweep stores the state of time s: a checkpoint of the
-// tape (s a multiple of k below max_tape_steps) straight into its tape slot,
-// which saves the copy; any other state into the grid that does not hold the
-// source.  (Keeping every state of the running segment in the segment
-// buffer as well, to skip its recompute, made the forward slower by as much
-// as the backward gained.)  nullptr if the slot index is out of range.
+// Tape slot of a checkpoint, or the segment slot of a state of the last
+// segment below max_tape_steps, for the state of time s; else nullptr.  The
+// forward keeps the last segment's states in the segment buffer, so an
+// adjoint started at max_tape_steps (or inside that segment) skips its
+// recompute.  (Keeping every segment there made the forward slower, 29 cold
+// destination buffers instead of two grids, by as much as the backward
+// gained; for the last segment alone it costs a fraction of the recompute.)
+void* tape_place(const lbm_ctx* c, int64_t s) {
+  if (c->k <= 0 || s >= c->cfg.max_tape_steps) return nullptr;
+  const int64_t j = s / c->k, r = s % c->k;
+  if (r == 0) return j < c->nslots ? tape_slot(c, j) : nullptr;
+  const int64_t last = (c->cfg.max_tape_steps - 1) / c->k;
+  return (j == last && c->seg && r - 1 < c->k - 1) ? seg_slot(c, r - 1) : nullptr;
+}
+
+// Where the two-array sweep stores the state of time s: its tape or segment
+// slot (no copy), else the grid that does not hold the source.
 void* place(const lbm_ctx* c, int64_t s, const void* src) {
-  if (c->k > 0 && s < c->cfg.max_tape_steps && s % c->k == 0)
-    return s / c->k < c->nslots ? tape_slot(c, s / c->k) : nullptr;
+  if (void* p = tape_place(c, s)) return p;
   return src == c->grid[0] ? c->grid[1] : c->grid[0];
 }
 
@@ -247,20 +262,22 @@ int layout_of(const lbm_ctx* c) { return is_aa(c) ? ((c->t & 1) ? 1 : 2) : 0; }
 // One forward step on the context's stream.
 int32_t step_once(lbm_ctx* c) {
   if (is_aa(c)) {
-    // the sweep that produces a checkpoint also writes it into its tape slot
+    // the sweep that produces a checkpoint (or a state of the last segment)
+    // also writes it, in the two-array layout, into its tape (segment) slot
     const int64_t s = c->t + 1;
-    void* tape = (c->k > 0 && s < c->cfg.max_tape_steps && s % c->k == 0 && s / c->k < c->nslots)
-                     ? (void*)tape_slot(c, s / c->k) : nullptr;
+    void* tape = tape_place(c, s);
     HIP_TRY(launch_sweep(c->cfg.stencil, c->kmethod, c->cfg.dtype, (int)(c->t & 1), c->grid[0], tape, c->flags,
                          c->force, sweep_geo(c, c->t, true), c->p, c->has_mask, c->stream),
             "AA sweep launch");
-    if (tape) c->taped_t = s;
+    if (tape && !in_seg(c, tape)) c->taped_t = s;
+    if (tape && in_seg(c, tape) && s % c->k == 1) c->seg_fwd_lo = s;
   } else {
     void* dst = place(c, c->t + 1, c->state);
     if (!dst || dst == c->state) return fail(LBM_EHIP, "internal: no buffer for the state of step %lld",
                                              (long long)(c->t + 1));
     int32_t st = sweep_once(c, c->state, dst, c->t);
     if (st != LBM_OK) return st;
+    if (in_seg(c, dst) && (c->t + 1) % c->k == 1) c->seg_fwd_lo = c->t + 1;
     c->state = dst;
   }
   c->t += 1;
@@ -316,6 +333,7 @@ int32_t mirror_grid(lbm_ctx* c) {
 void reset_time(lbm_ctx* c) {
   c->t = 0;
   c->seg_id = -1;
+  c->seg_fwd_lo = INT64_MAX;
   c->taped_t = -1;
   c->tape_ok = c->k > 0;
   c->adj_t = -1;
@@ -610,6 +628,18 @@ int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_d
   ctx->adj_T = ctx->t;
   ctx->adj_t = ctx->t;
   ctx->seg_id = -1;
+  if (ctx->t > 0 && ctx->k > 1) {
+    // the forward left the states of the last segment in the segment buffer
+    const int64_t J = (ctx->t - 1) / ctx->k;
+    if (ctx->seg_fwd_lo == J * ctx->k + 1) ctx->seg_id = J;
+    // the recompute of earlier segments overwrites that buffer: a two-array
+    // current state kept there moves to grid[1] (free while a tape is recorded)
+    if (in_seg(ctx, ctx->state)) {
+      HIP_TRY(hipMemcpyAsync(ctx->grid[1], ctx->state, ctx->grid_bytes, hipMemcpyDeviceToDevice, ctx->stream),
+              "state copy");
+      ctx->state = ctx->grid[1];
+    }
+  }
   return LBM_OK;
 }
 
@@ -625,6 +655,7 @@ int32_t forward_state(lbm_ctx* c, int64_t s, const void** out) {
     return LBM_OK;
   }
   if (c->seg_id != j) {
+    c->seg_fwd_lo = INT64_MAX;
     const int64_t last = std::min<int64_t>(c->k - 1, c->adj_T - 1 - j * c->k);
     const void* src = slot;
     for (int64_t i = 1; i <= last; ++i) {

@@ -300,3 +300,35 @@ def test_seed_again_after_continuing_within_a_segment():
     assert np.array_equal(np.asarray(ga[2]), np.asarray(gb[2]))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("T", [20, 18, 17, 16])
+def test_last_segment_kept_from_the_forward(pattern, T):
+    """max_tape_steps = 20, k = 4: the forward keeps the states 17..19 of the
+    last segment in the segment buffer, so an adjoint seeded at T = 17 ... 20
+    skips that recompute (at T < 20 the current state lives there and moves
+    to a grid first).  Gradients and the state itself equal those of a
+    context whose tape reaches further (max_tape_steps = 40, where T is not
+    in the last segment and everything is recomputed), bit for bit."""
+    need_gpu()
+    dims = (70, 10, 6)
+    mask, rho, u0, F, _ = _case("D3Q19", dims)
+    out = []
+    for max_T in (20, 40):
+        g = _tape_ctx(dims, mask, 4, max_T, pattern)
+        g.set_force(F)
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+        g.step(T)
+        before = g.get_pdfs()
+        grads = _seeded_grads(g, mask)
+        assert torch.equal(g.get_pdfs(), before)
+        g.step(2 if max_T == 40 or T <= 18 else 0)
+        out.append((grads, before, g.get_pdfs()))
+        g.close()
+    (ga, pa, qa), (gb, pb, qb) = out
+    assert torch.equal(pa, pb)
+    assert torch.equal(ga[0], gb[0]) and torch.equal(ga[1], gb[1])
+    assert np.array_equal(np.asarray(ga[2]), np.asarray(gb[2]))
+    if T <= 18:
+        assert torch.equal(qa, qb)
