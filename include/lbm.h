@@ -157,8 +157,10 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
  * AA even and odd kernels alternating with pattern 1; with launch_mode 0
  * small lattices replay a captured graph of 32 launches).  With the tape
  * enabled, the state at every multiple of k steps below max_tape_steps is
- * kept in the tape, in the two-array layout (the two-array sweep writes it
- * there directly; with AA it is copied out of the single array). */
+ * kept in the tape, in the two-array layout (the sweep that produces it
+ * writes it there directly), and so are the states of the last k-step
+ * segment below max_tape_steps, which an adjoint started in or at the end of
+ * that segment then need not recompute. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Readout of the stored (post-collision) state: rho = sum f,
