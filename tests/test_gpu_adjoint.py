@@ -165,8 +165,9 @@ def test_aa_adjoint_equals_two_arrays(stencil, dtype, T, k, method):
 
 
 def test_aa_adjoint_matches_oracle_with_moving_wall():
-    """AA adjoint against the oracle with a moving wall (the wall term is
-    rounded once more when a checkpoint is stored, so only to the FP64 bar)."""
+    """AA adjoint against the oracle with a moving wall (the initial
+    checkpoint is relaid out of the AA layout, which rounds the wall term once
+    more, so only to the FP64 bar)."""
     need_gpu()
     dims = (70, 10, 6)
     mask, rho, u0, F, T = _case("D3Q19", dims)
