@@ -153,8 +153,12 @@ int32_t lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u);
 int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
                              int32_t field_dtype);
 
-/* Advance n >= 0 time steps (one fused stream-pull-collide launch each, the
- * AA even and odd kernels alternating with pattern 1; with launch_mode 0
+/* Advance n >= 0 time steps.  One step is the pull streaming of Sec. IV-B
+ * (Fig. "stream-pull-collide": each cell gathers population q from its
+ * upstream neighbour x - c_q, with the bounce-back rule at solid neighbours)
+ * fused with the collision of the configured method, one launch per step;
+ * with pattern 1 the AA even and odd kernels of Sec. IV-B alternate on one
+ * array (Fig. "AA update pattern").  With launch_mode 0
  * small lattices replay a captured graph of 32 launches).  With the tape
  * enabled, the state at every multiple of k steps below max_tape_steps is
  * kept in the tape, in the two-array layout (the sweep that produces it
@@ -163,13 +167,15 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
  * that segment then need not recompute. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t n);
 
-/* Readout of the stored (post-collision) state: rho = sum f,
- * u = (sum c f - F/2) / rho_0 (rho_0 = rho when compressible).
+/* Readout of the stored (post-collision) state by Eq. (2): rho = sum f,
+ * u = (sum c f - F/2) / rho_0 (rho_0 = rho when compressible; the F/2 term
+ * makes u the Guo velocity of the collision that produced the state).
  * rho_dev: N or NULL, u_dev: 3*N or NULL, of type field_dtype. */
 int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t field_dtype);
 
-/* FP64 totals over fluid cells: out[0] = sum rho, out[1..3] = sum of the
- * momentum sum c f.  Synchronises.  LBM_ENONFINITE if any total is NaN/Inf
+/* FP64 totals over fluid cells of the moments of Eq. (2): out[0] = sum of
+ * rho = sum_q f_q, out[1..3] = sum of the momentum sum_q c_q f_q (without
+ * the F/2 shift).  Synchronises.  LBM_ENONFINITE if any total is NaN/Inf
  * (out is still written). */
 int32_t lbm_conserved(lbm_ctx* ctx, double out[4]);
 

@@ -8,8 +8,9 @@ seeded synthetic input generator (``paper_2001_11806_amd/inputs.py``), which
 holds none of the method's arithmetic.
 
 Everything here is written for clarity, not speed: numpy arrays over whole
-lattices or over lists of cells, float64 throughout, with the method's steps
-in the order the paper states them.
+lattices or over lists of cells (or plain loops over cells in the C++
+oracle), float64 throughout, with the method's steps in the order the paper
+states them.
 
 Module map
 ----------
@@ -26,6 +27,9 @@ run          initialisation, time stepping, readout, storage rounding
 adjoint      tangent-linear and discrete-adjoint maps of the SRT / TRT / MRT +
              Guo + bounce-back time step (not in the paper; derived by hand
              from the forward map)
+cpu          ctypes binding of lbm_oracle.cpp: a second, independent forward
+             oracle in plain C++17 loops with OpenMP over lattice rows (all
+             host cores), for lattices the numpy code is too slow for
 
 Functions without an independent pin say "parity unpinned" in their
 docstring.  All functions listed above are pinned by ``tests/test_oracle_*.py``.

@@ -7,6 +7,11 @@ velocity readout u_T.  The backward pass seeds the adjoint with dL/du_T,
 runs the hand-written adjoint sweep back to t = 0 (recomputing each
 checkpoint segment) and returns dL/du0 and dL/dF.  The lattice must have been
 created with ``checkpoint_every > 0`` and ``max_tape_steps >= nsteps``.
+
+A lattice holds one trajectory at a time: if the lattice is initialised,
+stepped or given a new force between this forward and its backward (for
+example by a second ``apply``), the backward raises instead of returning the
+gradients of the other run.
 """
 
 import torch
@@ -20,6 +25,7 @@ class LBMFunction(torch.autograd.Function):
         lbm.step(nsteps)
         _, u = lbm.macroscopic(dtype=u0.dtype)
         ctx.lbm = lbm
+        ctx.generation = lbm.generation
         ctx.nsteps = int(nsteps)
         ctx.F_meta = (F.dtype, F.device)
         return u
@@ -27,6 +33,10 @@ class LBMFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         lbm = ctx.lbm
+        if lbm.generation != ctx.generation:
+            raise RuntimeError("the lattice no longer holds the trajectory of this forward pass "
+                               "(it was initialised, stepped or given a new force since); "
+                               "run backward before reusing the lattice")
         lbm.adjoint_seed(grad_u.contiguous())
         lbm.adjoint_step(ctx.nsteps)
         du0, _, dF = lbm.adjoint_grads(dtype=grad_u.dtype)

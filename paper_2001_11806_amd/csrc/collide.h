@@ -592,8 +592,19 @@ template <class L, class R>
 __device__ __forceinline__ void collide_cumulant(R* f, const R* /*F*/, const CollideParams<R>& p) {
   constexpr int D = L::DIM;
   constexpr int NK = (D == 3) ? 3 : 1;
-  constexpr R cs2 = R(1.0 / 3.0);
-  constexpr R w1[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  // 1-D weights (1/6, 2/3, 1/6) and c_s^2 = 1/3 as constants of the compute
+  // type that keep the weight identities exact as real numbers: the centre
+  // weight is 2/3 rounded, the side weights are (1 - that) / 2 and c_s^2 is
+  // twice a side weight (both exact in R, by Sterbenz's lemma and a power-of-
+  // two scaling).  Rounding 1/6 and 2/3 separately would leave
+  // sum w = 1 + 3e-8 in FP32; that factor multiplies the smooth fields rho,
+  // rho u and drho in every cell and step, a coherent mass and momentum
+  // source that grows the FP32 velocity error linearly in time.  With the
+  // identities exact, what remains of the arithmetic error is rounding noise.
+  constexpr R w1c = R(2.0 / 3.0);
+  constexpr R w1s = (R(1) - w1c) * R(0.5);
+  constexpr R cs2 = R(2) * w1s;
+  constexpr R w1[3] = {w1s, w1c, w1s};
   // ---- raw moments of order <= 2 by per-axis sums; index i = c + 1
   R X0[3][NK], X1[3][NK], X2[3][NK];   // x pass: sum, f+ - f-, f+ + f- along x
 #pragma unroll

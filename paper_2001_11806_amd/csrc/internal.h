@@ -43,6 +43,10 @@ struct Params {
 
 inline int64_t num_blocks(const Geo& g) { return (int64_t)g.nxb * g.ny * g.nz; }
 
+// Record the thread-local message lbm_last_error() returns (printf format)
+// and return `code`.
+int32_t set_last_error(int32_t code, const char* fmt, ...);
+
 // forward
 // phase -1: two-array sweep src -> dst; 0 / 1: AA even / odd kernel in place on src,
 // with dst (if not null) receiving the produced state in the two-array layout

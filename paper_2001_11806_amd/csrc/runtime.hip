@@ -28,6 +28,20 @@ int32_t fail(int32_t code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+int32_t lbm::set_last_error(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+namespace {
+
 int32_t hip_fail(hipError_t e, const char* what) {
   return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }

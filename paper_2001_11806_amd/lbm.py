@@ -166,6 +166,9 @@ class LBM:
             _check(self.lib.lbm_create(ctypes.byref(self.cfg), mptr, ctypes.c_void_p(stream.cuda_stream),
                                        ctypes.byref(h)))
         self.h = h
+        # bumped by every call that changes the forward trajectory, so that a
+        # pending autograd graph can tell whether the lattice still holds it
+        self.generation = 0
 
     # ------------------------------------------------------------ helpers
     def _shape3(self):
@@ -198,6 +201,7 @@ class LBM:
 
     # ------------------------------------------------------------ API
     def set_force(self, F=None, profile=None):
+        self.generation += 1
         if F is not None:
             arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(F, dtype=np.float64).reshape(3)])
             _check(self.lib.lbm_set_force(self.h, arr, None))
@@ -210,10 +214,12 @@ class LBM:
             _check(self.lib.lbm_set_force(self.h, None, None))
 
     def set_wall_velocity(self, wall_type, u):
+        self.generation += 1
         arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(u, dtype=np.float64).reshape(3)])
         _check(self.lib.lbm_set_wall_velocity(self.h, int(wall_type), arr))
 
     def init_equilibrium(self, rho=None, u=None):
+        self.generation += 1
         r, dr = self._field(rho, 1, "rho")
         v, dv = self._field(u, 3, "u")
         dt = dr if dr is not None else (dv if dv is not None else 0)
@@ -224,6 +230,7 @@ class LBM:
         self._keep = (r, v)   # keep alive until the stream has consumed them
 
     def step(self, n=1):
+        self.generation += 1
         _check(self.lib.lbm_step(self.h, int(n)))
 
     @property
@@ -252,6 +259,7 @@ class LBM:
         return P
 
     def set_pdfs(self, P):
+        self.generation += 1
         P, _ = self._field(P, self.Q, "pdfs")
         P = P.to(self.torch.float64).contiguous()
         _check(self.lib.lbm_set_pdfs(self.h, _ptr(P)))

@@ -15,6 +15,7 @@ import pytest
 from tests.gpu_common import (RATES, case_dims, make_gpu, need_gpu, oracle_cfg, rel_l2, seeded_fields,
                               to_np, torch, ulp_of)
 from oracle import run as orun
+from paper_2001_11806_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -517,3 +518,41 @@ def test_block_orders_match_oracle(dims, stencil, method, dtype, pattern):
         if dtype == "f64":
             assert np.max(np.abs(to_np(g.get_pdfs()) - P)) <= 1e-13, done
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+def test_kbc_near_equilibrium_parity(stencil, dtype):
+    """Entropic KBC close to equilibrium, as in the Kolmogorov workload: no
+    walls, rho = 1, u i.i.d. uniform +-1e-3 (seed 5), the per-row force
+    1e-6 sin(2 pi y / ny).  There the higher-order non-equilibrium dh is of
+    order 1e-4 of the weights, and omega_h = 1 + <.,dh>_E / <dh,dh>_E divides
+    two small quantities.  12 steps against the oracle at the same bars as
+    far from equilibrium: FP64 |dP| <= 1e-13 and relative L2 of u <= 1e-12,
+    FP32 relative L2 of u <= 1e-5."""
+    need_gpu()
+    dims = case_dims(stencil)
+    nx, ny, nz = dims
+    u = inputs.uniform_noise_velocity(dims, 1e-3, 5, None)
+    if stencil == "D2Q9":
+        u[2] = 0
+    rho = np.ones((nz, ny, nx))
+    F = inputs.kolmogorov_force_profile(ny, 1e-6)
+    rates = _rates("KBC")
+    print("case KBC near equilibrium", stencil, dtype, dims, flush=True)
+    g = make_gpu(stencil, "KBC", dtype, dims, None, rates)
+    g.set_force(profile=F)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(STEPS)
+    P_gpu = to_np(g.get_pdfs())
+    _, ug = (to_np(t) for t in g.macroscopic())
+    g.close()
+    cfg = oracle_cfg(stencil, "KBC", "f64", rates)
+    Ff = orun.force_field(F, dims)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u), STEPS, None, Ff)
+    _, uo = orun.readout(cfg, P, None, Ff)
+    err_u = rel_l2(ug, uo)
+    print("rel L2 u %.3e, max |dP| %.2e" % (err_u, np.max(np.abs(P_gpu - P))))
+    assert err_u <= BOUND_U[dtype]
+    if dtype == "f64":
+        assert np.max(np.abs(P_gpu - P)) <= 1e-13
