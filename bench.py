@@ -178,21 +178,7 @@ def main():
     torch.cuda.empty_cache()
 
     if want("copy"):
-        for dt, eb in (("f64", 8), ("f32", 4), ("f16", 2)):
-            N = n ** 3
-            src = torch.empty(19 * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
-            dst = torch.empty_like(src)
-            st = torch.cuda.current_stream(dev)
-            for _ in range(3):
-                copy_q(src, dst, N, 19, eb, st)
-            with Timer(torch, st) as t:
-                for _ in range(20):
-                    copy_q(src, dst, N, 19, eb, st)
-            gbps = 2 * 19 * N * eb * 20 / (t.ms / 1e3) / 1e9
-            extras["copy_q19_%s_256" % dt] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
-            log("copy-Q19 %s: %.0f GB/s" % (dt, gbps))
-            del src, dst
-        torch.cuda.empty_cache()
+        extras.update(bench_copies(torch, copy_q, Timer, dev))
 
     if want("c3"):
         # the full 500-step run in every storage type; FP64 on the same GPU
@@ -261,8 +247,12 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inputs)
 
-    extras["c2_d3q19_trt_256_f64"] = {"fluid_mlups": head["fluid_mlups"]}   # the headline, fluid cells only
-    traffic = read_traffic("sweep_d3q19_trt_256_f64_traffic.txt")
+    # the headline, fluid cells only, and its copy line / counter figures
+    extras["c2_d3q19_trt_256_f64"] = {"fluid_mlups": head["fluid_mlups"], "achieved_GBps": head["achieved_GBps"],
+                                      "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"]}
+    attach_lines(extras)
+    traffic = read_traffic(MATCH["c2_d3q19_trt_256_f64"][1])
+    line = MATCH["c2_d3q19_trt_256_f64"][0]
     result = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -284,15 +274,121 @@ def main():
                      "frac": head["hbm_frac"], "traffic": traffic,
                      "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
                      "kernel": "k_sweep<D3Q19, TRT, double>",
-                     # attainable line: the 19-plane FP64 copy of the same size, same run
-                     "copy_line_GBps": extras.get("copy_q19_f64_256", {}).get("GBps"),
-                     "frac_of_copy_line": (head["achieved_GBps"] / extras["copy_q19_f64_256"]["GBps"]
-                                           if "copy_q19_f64_256" in extras else None)},
+                     # attainable line: the 19-plane FP64 copy of the same size in the
+                     # sweep's launch shape, same run; and a plain device-to-device memcpy
+                     "copy_line_GBps": extras.get(line, {}).get("GBps"),
+                     "frac_of_copy_line": (head["achieved_GBps"] / extras[line]["GBps"]
+                                           if line in extras else None),
+                     "memcpy_d2d_GBps": extras.get("memcpy_d2d_4GiB", {}).get("GBps")},
         "cpu_baseline": cpu,
         "extras": extras,
         "wall_s": round(time.time() - t_start, 1),
     }
     print(json.dumps(result))
+
+
+# Copy references (the paper's multi-stream copy benchmark, Sec. V-A, Tab. III):
+# Q read and Q write SoA streams of the workload's size and element type, in
+# the launch shape (waves per CU, 0 = full occupancy) of the sweep compared
+# with them.  Key -> (Q, lattice edge, storage, element bytes, waves per CU).
+COPIES = {
+    "copy_q19_f64_256_w12": (19, 256, "f64", 8, 12),   # C2 FP64 two-array sweep
+    "copy_q19_f64_256_w0": (19, 256, "f64", 8, 0),     # C2 FP64 AA sweeps
+    "copy_q19_f32_256_w16": (19, 256, "f32", 4, 16),   # C2 FP32 two-array sweep
+    "copy_q19_f16_256_w0": (19, 256, "f16", 2, 0),
+    "copy_q27_f64_384_w12": (27, 384, "f64", 8, 12),   # C3 FP64 (error reference)
+    "copy_q27_f32_384_w0": (27, 384, "f32", 4, 0),     # C3 FP32 cumulant
+    "copy_q27_f16_384_w0": (27, 384, "f16", 2, 0),     # C3 BF16 / FP16 cumulant
+    "copy_q27_f64_512_w12": (27, 512, "f64", 8, 12),   # C5 FP64 MRT
+    "copy_q27_f16_512_w0": (27, 512, "f16", 2, 0),     # C5 FP16 MRT
+}
+# workload -> (matching copy line, committed counter summary of its sweep kernel)
+MATCH = {
+    "c2_d3q19_trt_256_f64": ("copy_q19_f64_256_w12", "sweep_d3q19_trt_256_f64_traffic.txt"),
+    "c2_d3q19_trt_256_f32": ("copy_q19_f32_256_w16", "sweep_d3q19_trt_256_f32_traffic.txt"),
+    "c2_d3q19_trt_256_f64_aa": ("copy_q19_f64_256_w0", "sweep_aa_d3q19_trt_256_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f64": ("copy_q27_f64_384_w12", "sweep_d3q27_cumulant_384_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f32": ("copy_q27_f32_384_w0", "sweep_d3q27_cumulant_384_f32_traffic.txt"),
+    "c3_d3q27_cumulant_384_bf16": ("copy_q27_f16_384_w0", "sweep_d3q27_cumulant_384_bf16_traffic.txt"),
+    "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0", "sweep_d3q27_cumulant_384_f16_traffic.txt"),
+    "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12", "sweep_d3q27_mrt_512_f64_traffic.txt"),
+    "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0", "sweep_d3q27_mrt_512_f16_traffic.txt"),
+}
+
+
+def bench_copies(torch, copy_q, Timer, dev):
+    """Copy lines of every configured workload, plus two copies that owe
+    nothing to this library: hipMemcpyAsync device to device (called
+    directly in the HIP runtime torch loaded) and torch's Tensor.copy_, each
+    on a 4 GiB buffer."""
+    import ctypes
+    out = {}
+    st = torch.cuda.current_stream(dev)
+    for key, (q, n, dt, eb, waves) in COPIES.items():
+        N = n ** 3
+        src = torch.empty(q * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            copy_q(src, dst, N, q, eb, st, waves)
+        with Timer(torch, st) as t:
+            for _ in range(20):
+                copy_q(src, dst, N, q, eb, st, waves)
+        gbps = 2 * q * N * eb * 20 / (t.ms / 1e3) / 1e9
+        out[key] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
+        log("%s: %.0f GB/s" % (key, gbps))
+        del src, dst
+        torch.cuda.empty_cache()
+    nbytes = 4 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    try:
+        hip = ctypes.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD)   # the runtime already in the process
+        hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.c_void_p]
+        hip.hipMemcpyAsync.restype = ctypes.c_int
+
+        def memcpy():
+            rc = hip.hipMemcpyAsync(dst.data_ptr(), src.data_ptr(), nbytes, 3, st.cuda_stream)  # 3: D2D
+            if rc != 0:
+                raise RuntimeError("hipMemcpyAsync returned %d" % rc)
+        for _ in range(2):
+            memcpy()
+        with Timer(torch, st) as t:
+            for _ in range(10):
+                memcpy()
+        gbps = 2 * nbytes * 10 / (t.ms / 1e3) / 1e9
+        out["memcpy_d2d_4GiB"] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
+        log("hipMemcpyAsync D2D 4 GiB: %.0f GB/s" % gbps)
+    except (OSError, RuntimeError) as e:
+        out["memcpy_d2d_4GiB"] = {"GBps": None, "error": str(e)}
+    for _ in range(2):
+        dst.copy_(src)
+    with Timer(torch, st) as t:
+        for _ in range(10):
+            dst.copy_(src)
+    gbps = 2 * nbytes * 10 / (t.ms / 1e3) / 1e9
+    out["torch_copy_4GiB"] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
+    log("torch copy_ 4 GiB: %.0f GB/s" % gbps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def attach_lines(extras):
+    """Per workload: the matching copy line, the fraction of it reached, and
+    the counter-measured HBM bytes per launch while the committed summary
+    matches the kernel sources."""
+    for w, (line, prof) in MATCH.items():
+        if w not in extras:
+            continue
+        r = extras[w]
+        if line in extras and "achieved_GBps" in r:
+            r["copy_line"] = line
+            r["frac_of_copy_line"] = r["achieved_GBps"] / extras[line]["GBps"]
+        tr = read_traffic(prof)
+        r["traffic"] = tr
+        if tr is not None and "algorithmic_bytes_per_launch" in r:
+            r["traffic_over_algorithmic"] = tr / r["algorithmic_bytes_per_launch"]
 
 
 def bench_methods(torch, LBM, inputs, Timer, run_forward):
@@ -382,29 +478,56 @@ def bench_adjoint(torch, LBM, inputs, Timer, pattern=0):
 
 
 def cpu_baseline(inputs):
-    """The oracle as it stands, one host thread, on a bounded sample of the
-    headline workload: a 256 x 64 x 32 slice of the channel, stepped until
-    at least 10 s of work (at most 60 steps)."""
-    from threadpoolctl import threadpool_limits
-    from oracle import run as orun
-    dims = (256, 64, 32)
-    mask = inputs.channel_mask(*dims)
-    u = inputs.uniform_noise_velocity(dims, 1e-3, 2, mask)
-    cfg = orun.Config("D3Q19", "TRT", dict(omega=1 / 0.8, magic=3 / 16, omega_odd=0.0))
-    Ff = orun.force_field(np.array([1e-6, 0, 0]), dims)
-    with threadpool_limits(1):
-        P = orun.init_equilibrium(cfg, np.ones((32, 64, 256)), u, mask)
+    """The C++ FP64 oracle as it stands (plain loops, OpenMP over rows) on all
+    the host threads it sees, on bounded samples: the headline workload on
+    its full 256^3 channel for as many steps as fit in about 15 s (at least
+    one), then a 384 x 384 x 16 slab of the cumulant workload and a
+    512 x 512 x 8 slab of the Kolmogorov MRT workload, two steps each (their
+    full lattices would need 24 GB and 58 GB of host memory for two FP64
+    arrays).  Returns the headline figure and the per-workload samples."""
+    from oracle import cpu as ocpu, run as orun
+    threads = ocpu.num_threads()
+    host = {"threads": threads, "os_cpu_count": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+    def timed(cfg, P, steps, mask=None, force=None):
         t0 = time.time()
-        steps = 0
-        while steps < 60 and (steps < 2 or time.time() - t0 < 10.0):
-            P = orun.step(cfg, P, mask, Ff)
-            steps += 1
-        dt = time.time() - t0
-    cells = dims[0] * dims[1] * dims[2]
-    log("CPU oracle: %.2f MLUPS (%d steps, %.1f s)" % (cells * steps / dt / 1e6, steps, dt))
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "numpy FP64 oracle, D3Q19 TRT channel 256x64x32 (same recipe as the headline), "
-                      "%d steps, %.1f s, one host thread" % (steps, dt)}
+        P = ocpu.run(cfg, P, steps, mask, force)
+        return P, time.time() - t0
+
+    n = 256
+    mask, _, u = inputs.channel_flow(n, seed=2, amp=1e-3)
+    cfg = orun.Config("D3Q19", "TRT", dict(omega=1 / 0.8, magic=3 / 16, omega_odd=0.0))
+    F = np.array([1e-6, 0.0, 0.0])
+    P = ocpu.init_equilibrium(cfg, None, u, mask)
+    del u
+    P, t1 = timed(cfg, P, 1, mask, F)
+    steps = int(max(1, min(20, 15.0 // max(t1, 1e-3))))
+    P, dt = timed(cfg, P, steps, mask, F)
+    del P
+    head = n ** 3 * steps / dt / 1e6
+    log("CPU oracle, C2 256^3: %.1f MLUPS (%d steps, %.1f s, %d threads)" % (head, steps, dt, threads))
+    samples = {"c2_d3q19_trt_256_f64": {"mlups": head, "steps": steps, "seconds": dt, "lattice": [n, n, n]}}
+    cells = np.arange(384 * 384 * 16)
+    u3 = inputs.solenoidal_velocity_at(384, inputs.solenoidal_modes(seed=3), cells).reshape(3, 16, 384, 384)
+    c3 = orun.Config("D3Q27", "CUMULANT", dict(omega=1 / 0.55, omega_bulk=1.0, omega_hi=(1.0,) * 4))
+    P, dt = timed(c3, ocpu.init_equilibrium(c3, None, u3), 2)
+    samples["c3_d3q27_cumulant_f64"] = {"mlups": u3[0].size * 2 / dt / 1e6, "steps": 2, "seconds": dt,
+                                        "lattice": [384, 384, 16]}
+    del P, u3
+    u5 = inputs.uniform_noise_velocity((512, 512, 8), 1e-3, 5, None)
+    c5 = orun.Config("D3Q27", "MRT", dict(omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.0,) * 4))
+    prof = inputs.kolmogorov_force_profile(512, 1e-6)
+    P, dt = timed(c5, ocpu.init_equilibrium(c5, None, u5), 2, None, prof)
+    samples["c5_d3q27_mrt_f64"] = {"mlups": u5[0].size * 2 / dt / 1e6, "steps": 2, "seconds": dt,
+                                   "lattice": [512, 512, 8]}
+    del P, u5
+    log("CPU oracle samples: C3 %.2f MLUPS, C5 %.2f MLUPS" % (samples["c3_d3q27_cumulant_f64"]["mlups"],
+                                                              samples["c5_d3q27_mrt_f64"]["mlups"]))
+    return {"value": head, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "C++ FP64 oracle (OpenMP, %d threads), the headline D3Q19 TRT channel on its full 256^3 "
+                      "lattice, %d steps in %.1f s" % (threads, steps, samples["c2_d3q19_trt_256_f64"]["seconds"]),
+            "host": host, "samples": samples}
 
 
 if __name__ == "__main__":

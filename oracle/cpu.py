@@ -23,6 +23,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.cpp")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
+# the same source with long double for every value (x87 extended precision,
+# 64-bit significand): measures the FP64 oracle's own rounding floor
+LIB_LD = os.path.join(HERE, "liblbm_oracle_ld.so")
 FLAGS = ["-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 STENCIL = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
@@ -30,37 +33,47 @@ METHOD = {"SRT": 0, "TRT": 1, "MRT": 2, "CUMULANT": 3}
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 
 
-class OrcConfig(ctypes.Structure):
-    _fields_ = [("stencil", ctypes.c_int32), ("method", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("compressible", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("omega", ctypes.c_double), ("omega_bulk", ctypes.c_double),
-                ("omega_odd", ctypes.c_double), ("magic", ctypes.c_double), ("omega_hi", ctypes.c_double * 4),
-                ("rho0", ctypes.c_double)]
+def _config_type(R):
+    class OrcConfig(ctypes.Structure):
+        _fields_ = [("stencil", ctypes.c_int32), ("method", ctypes.c_int32), ("storage", ctypes.c_int32),
+                    ("compressible", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                    ("nz", ctypes.c_int32), ("omega", R), ("omega_bulk", R), ("omega_odd", R), ("magic", R),
+                    ("omega_hi", R * 4), ("rho0", R)]
+    return OrcConfig
+
+
+# ctypes struct and numpy element type per precision ("f64" or "ld")
+CONFIG = {"f64": _config_type(ctypes.c_double), "ld": _config_type(ctypes.c_longdouble)}
+REAL = {"f64": np.float64, "ld": np.longdouble}
+OrcConfig = CONFIG["f64"]
 
 
 def build(verbose=True):
-    """Compile the oracle library with g++ (OpenMP); always recompiles."""
-    tmp = LIB + ".tmp"
-    subprocess.check_call(["g++", *FLAGS, SRC, "-o", tmp])
-    os.replace(tmp, LIB)
-    if verbose:
-        print("built", LIB)
+    """Compile the oracle library (FP64, and the long double variant) with
+    g++ and OpenMP; always recompiles."""
+    for lib, extra in ((LIB, []), (LIB_LD, ["-DORC_REAL=long double"])):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["g++", *FLAGS, *extra, SRC, "-o", tmp])
+        os.replace(tmp, lib)
+        if verbose:
+            print("built", lib)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def load():
-    """Load the oracle library, building it first if it is not there."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB):
+def load(precision="f64"):
+    """Load the oracle library of the given precision ("f64" or "ld"),
+    building it first if it is not there."""
+    if precision in _libs:
+        return _libs[precision]
+    path = {"f64": LIB, "ld": LIB_LD}[precision]
+    if not os.path.exists(path):
         build(verbose=False)
-    lib = ctypes.CDLL(LIB)
+    lib = ctypes.CDLL(path)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    C = ctypes.POINTER(OrcConfig)
+    C = ctypes.POINTER(CONFIG[precision])
     for name, args in {"orc_init": [C, P, P, P, P], "orc_run": [C, P, P, P, P, I32, I32],
                        "orc_readout": [C, P, P, P, P, P], "orc_conserved": [C, P, P, P],
                        "orc_collide_cells": [C, P, P, I64, P], "orc_mrt_basis": [C, P, P]}.items():
@@ -69,7 +82,7 @@ def load():
         fn.restype = I32
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = I32
-    _lib = lib
+    _libs[precision] = lib
     return lib
 
 
@@ -78,10 +91,10 @@ def num_threads():
     return int(load().orc_num_threads())
 
 
-def _cfg(cfg, dims):
+def _cfg(cfg, dims, precision="f64"):
     """Translate an ``oracle.run.Config`` and lattice dims into the C struct."""
     r = cfg.rates
-    c = OrcConfig()
+    c = CONFIG[precision]()
     c.stencil = STENCIL[cfg.lat.name]
     c.method = METHOD[cfg.method]
     c.storage = STORAGE[cfg.storage]
@@ -110,10 +123,10 @@ def _mask(mask):
     return None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
 
 
-def _force(force, ny):
+def _force(force, ny, precision="f64"):
     if force is None:
         return None
-    F = np.asarray(force, dtype=np.float64)
+    F = np.asarray(force, dtype=REAL[precision])
     if F.shape == (3,):
         F = np.broadcast_to(F, (ny, 3))
     if F.shape != (ny, 3):
@@ -121,10 +134,10 @@ def _force(force, ny):
     return np.ascontiguousarray(F)
 
 
-def _walls(wall_velocity):
+def _walls(wall_velocity, precision="f64"):
     if wall_velocity is None:
         return None
-    W = np.zeros((128, 3))
+    W = np.zeros((128, 3), dtype=REAL[precision])
     w = np.asarray(wall_velocity, dtype=np.float64)
     W[:w.shape[0]] = w
     return W
@@ -135,36 +148,41 @@ def _check(st, what):
         raise ValueError("C++ oracle %s failed (status %d)" % (what, st))
 
 
-def init_equilibrium(cfg, rho, u, mask=None):
+def init_equilibrium(cfg, rho, u, mask=None, precision="f64"):
     """P^0 = f^eq(rho, u) (Eq. 3) at fluid cells, w rho_0 at solid cells,
-    rounded into the storage type.  rho may be None (rho_0 everywhere)."""
-    u = np.ascontiguousarray(u, dtype=np.float64)
+    rounded into the storage type.  rho may be None (rho_0 everywhere).
+    ``precision`` "ld" computes in long double and returns np.longdouble."""
+    R = REAL[precision]
+    u = np.ascontiguousarray(u, dtype=R)
     dims = _dims_of(u)
-    r = None if rho is None else np.ascontiguousarray(np.broadcast_to(rho, u.shape[1:]), dtype=np.float64)
-    P = np.empty((cfg.lat.Q,) + u.shape[1:])
-    _check(load().orc_init(ctypes.byref(_cfg(cfg, dims)), _ptr(_mask(mask)), _ptr(r), _ptr(u), _ptr(P)), "init")
+    r = None if rho is None else np.ascontiguousarray(np.broadcast_to(rho, u.shape[1:]), dtype=R)
+    P = np.empty((cfg.lat.Q,) + u.shape[1:], dtype=R)
+    _check(load(precision).orc_init(ctypes.byref(_cfg(cfg, dims, precision)), _ptr(_mask(mask)), _ptr(r), _ptr(u),
+                                    _ptr(P)), "init")
     return P
 
 
-def run(cfg, P, nsteps, mask=None, force=None, wall_velocity=None, threads=0):
+def run(cfg, P, nsteps, mask=None, force=None, wall_velocity=None, threads=0, precision="f64"):
     """``nsteps`` stream-pull-collide steps from P; returns the new state
     (P itself is not modified)."""
-    P = np.array(P, dtype=np.float64, order="C", copy=True)
+    P = np.array(P, dtype=REAL[precision], order="C", copy=True)
     dims = _dims_of(P)
-    st = load().orc_run(ctypes.byref(_cfg(cfg, dims)), _ptr(_mask(mask)), _ptr(_force(force, dims[1])),
-                        _ptr(_walls(wall_velocity)), _ptr(P), int(nsteps), int(threads))
+    st = load(precision).orc_run(ctypes.byref(_cfg(cfg, dims, precision)), _ptr(_mask(mask)),
+                                 _ptr(_force(force, dims[1], precision)), _ptr(_walls(wall_velocity, precision)),
+                                 _ptr(P), int(nsteps), int(threads))
     _check(st, "run")
     return P
 
 
-def readout(cfg, P, mask=None, force=None):
+def readout(cfg, P, mask=None, force=None, precision="f64"):
     """rho, u of a stored post-collision state (solid cells read 0)."""
-    P = np.ascontiguousarray(P, dtype=np.float64)
+    R = REAL[precision]
+    P = np.ascontiguousarray(P, dtype=R)
     dims = _dims_of(P)
-    rho = np.empty(P.shape[1:])
-    u = np.empty((3,) + P.shape[1:])
-    st = load().orc_readout(ctypes.byref(_cfg(cfg, dims)), _ptr(_mask(mask)), _ptr(_force(force, dims[1])),
-                            _ptr(P), _ptr(rho), _ptr(u))
+    rho = np.empty(P.shape[1:], dtype=R)
+    u = np.empty((3,) + P.shape[1:], dtype=R)
+    st = load(precision).orc_readout(ctypes.byref(_cfg(cfg, dims, precision)), _ptr(_mask(mask)),
+                                     _ptr(_force(force, dims[1], precision)), _ptr(P), _ptr(rho), _ptr(u))
     _check(st, "readout")
     return rho, u
 

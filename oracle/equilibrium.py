@@ -12,9 +12,19 @@ import numpy as np
 from .lattice import CS2, CS2_EXACT
 
 
+def _real_or_complex(a):
+    """The input as a float64 array, keeping a wider or complex floating
+    type: the complex-step derivative (``adjoint.tangent_complex_step``)
+    runs the forward map on complex values, and the FP64 rounding floor of
+    the oracle is measured against a run in extended precision
+    (``np.longdouble``).  Integer and float64 inputs give float64."""
+    a = np.asarray(a)
+    return a.astype(np.result_type(a.dtype, np.float64), copy=False)
+
+
 def _bcast(a, ndim):
     """Reshape a (3,)- or (3, ...)-array so it broadcasts against (3, *cells)."""
-    a = np.asarray(a, dtype=np.float64)
+    a = _real_or_complex(a)
     return a.reshape(a.shape + (1,) * (ndim + 1 - a.ndim))
 
 
@@ -48,8 +58,8 @@ def equilibrium(lat, rho, u, rho0=1.0, compressible=True):
     The (c.u)^2 / u.u pair is the paper's u_a u_b (c_a c_b - c_s^2 delta_ab)
     term written out.
     """
-    rho = np.asarray(rho, dtype=np.float64)
-    u = np.asarray(u, dtype=np.float64)
+    rho = _real_or_complex(rho)
+    u = _real_or_complex(u)
     cu = np.tensordot(lat.c.astype(np.float64), u, axes=(1, 0))
     usq = (u * u).sum(axis=0)
     r0 = rho if compressible else rho0
@@ -63,7 +73,7 @@ def guo_source(lat, u, force):
     S_q = w_q [ (c_q - u).F / c_s^2 + (c_q.u)(c_q.F) / c_s^4 ].
     Its moments are sum S = 0, sum c S = F, sum c_a c_b S = u_a F_b + F_a u_b.
     """
-    u = np.asarray(u, dtype=np.float64)
+    u = _real_or_complex(u)
     F = _bcast(force, u.ndim - 1) * np.ones_like(u)
     c = lat.c.astype(np.float64)
     cu = np.tensordot(c, u, axes=(1, 0))

@@ -5,7 +5,10 @@
 // baseline of the benchmark load this library.  It shares no code, tables or
 // constants with the HIP library, and it is written for clarity, not speed:
 // one cell at a time, the method's steps in the order the paper states them,
-// dense loops over directions and moments, double precision throughout.
+// dense loops over directions and moments, double precision throughout.  The
+// same source also builds with long double (64-bit significand) for every
+// value and argument: that build serves only to measure how far the FP64
+// oracle's own rounding moves a result.
 //
 // What it computes (paper: "lbmpy: Automatic code generation for efficient
 // parallel lattice Boltzmann methods"):
@@ -39,15 +42,23 @@
 #include <omp.h>
 #endif
 
+// Floating-point type of every value and argument: double, or long double
+// (x87 extended, 64-bit significand) in the build that measures the FP64
+// rounding floor (-DORC_REAL="long double").
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
+
 namespace {
 
-constexpr double CS2 = 1.0 / 3.0;
+constexpr real CS2 = real(1) / 3;
 
 // ------------------------------------------------------------------ lattice
 struct Lattice {
   int d = 0, Q = 0, h = 0;
   int c[27][3] = {};
-  double w[27] = {};
+  real w[27] = {};
   int opp[27] = {};
 };
 
@@ -83,19 +94,19 @@ bool make_lattice(int stencil, Lattice& L) {
     L.opp[q] = q == 0 ? 0 : (q <= L.h ? q + L.h : q - L.h);
     const int s = L.c[q][0] * L.c[q][0] + L.c[q][1] * L.c[q][1] + L.c[q][2] * L.c[q][2];
     if (stencil == 0) {
-      L.w[q] = s == 0 ? 4.0 / 9.0 : (s == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+      L.w[q] = s == 0 ? real(4) / 9 : (s == 1 ? real(1) / 9 : real(1) / 36);
     } else if (stencil == 1) {
-      L.w[q] = s == 0 ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+      L.w[q] = s == 0 ? real(1) / 3 : (s == 1 ? real(1) / 18 : real(1) / 36);
     } else {
-      L.w[q] = s == 0 ? 8.0 / 27.0 : (s == 1 ? 2.0 / 27.0 : (s == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+      L.w[q] = s == 0 ? real(8) / 27 : (s == 1 ? real(2) / 27 : (s == 2 ? real(1) / 54 : real(1) / 216));
     }
   }
   return true;
 }
 
 // integer power of a velocity component (exponent 0, 1 or 2)
-double ipow(int c, int e) {
-  double r = 1.0;
+real ipow(int c, int e) {
+  real r = 1.0;
   for (int i = 0; i < e; ++i) r *= c;
   return r;
 }
@@ -106,9 +117,9 @@ enum { SRT = 0, TRT = 1, MRT = 2, CUMULANT = 3 };
 struct Method {
   Lattice L;
   int method = 0, storage = 0, compressible = 1;
-  double omega = 0, omega_bulk = 0, omega_odd = 0, hi[4] = {0, 0, 0, 0}, rho0 = 1;
+  real omega = 0, omega_bulk = 0, omega_odd = 0, hi[4] = {0, 0, 0, 0}, rho0 = 1;
   // MRT: weighted-orthogonal basis rows M[k][q], their inverse, per-row rate
-  std::vector<double> M, Minv, rate;
+  std::vector<real> M, Minv, rate;
   // cumulants: monomial exponents and, per exponent, its set partitions
   // (each partition a list of block exponents)
   std::vector<int> ex;                                   // n_ex * 3
@@ -136,7 +147,7 @@ void build_mrt(Method& m) {
   const Lattice& L = m.L;
   const int Q = L.Q;
   struct Row {
-    std::vector<double> v;
+    std::vector<real> v;
     int group;   // 0 conserved, 1 shear, 2 bulk, 3.. order
   };
   std::vector<int> exps;   // candidate exponent triples
@@ -154,7 +165,7 @@ void build_mrt(Method& m) {
           exps.push_back(c);
         }
   auto mono = [&](int i) {
-    std::vector<double> v(Q);
+    std::vector<real> v(Q);
     for (int q = 0; q < Q; ++q)
       v[q] = ipow(L.c[q][0], exps[3 * i]) * ipow(L.c[q][1], exps[3 * i + 1]) * ipow(L.c[q][2], exps[3 * i + 2]);
     return v;
@@ -169,9 +180,9 @@ void build_mrt(Method& m) {
     else if (ord == 2 && mx == 2) diag.push_back(i);
     else if (ord >= 3) high.push_back({mono(i), ord});
   }
-  std::vector<double> d0 = mono(diag[0]);
+  std::vector<real> d0 = mono(diag[0]);
   for (size_t k = 1; k < diag.size(); ++k) {
-    std::vector<double> dk = mono(diag[k]), v(Q);
+    std::vector<real> dk = mono(diag[k]), v(Q);
     for (int q = 0; q < Q; ++q) v[q] = d0[q] - dk[q];
     second.push_back({v, 1});
   }
@@ -180,9 +191,9 @@ void build_mrt(Method& m) {
     const int mx = std::max(exps[3 * i], std::max(exps[3 * i + 1], exps[3 * i + 2]));
     if (ord == 2 && mx == 1) second.push_back({mono(i), 1});
   }
-  std::vector<double> bulk(Q, 0.0);
+  std::vector<real> bulk(Q, 0.0);
   for (int i : diag) {
-    std::vector<double> v = mono(i);
+    std::vector<real> v = mono(i);
     for (int q = 0; q < Q; ++q) bulk[q] += v[q];
   }
   second.push_back({bulk, 2});
@@ -192,7 +203,7 @@ void build_mrt(Method& m) {
   // weighted Gram-Schmidt
   for (size_t k = 0; k < rows.size(); ++k)
     for (size_t j = 0; j < k; ++j) {
-      double num = 0, den = 0;
+      real num = 0, den = 0;
       for (int q = 0; q < Q; ++q) {
         num += L.w[q] * rows[k].v[q] * rows[j].v[q];
         den += L.w[q] * rows[j].v[q] * rows[j].v[q];
@@ -203,7 +214,7 @@ void build_mrt(Method& m) {
   m.Minv.assign((size_t)Q * Q, 0.0);
   m.rate.assign(Q, 0.0);
   for (int k = 0; k < Q; ++k) {
-    double dk = 0;
+    real dk = 0;
     for (int q = 0; q < Q; ++q) {
       m.M[(size_t)k * Q + q] = rows[k].v[q];
       dk += L.w[q] * rows[k].v[q] * rows[k].v[q];
@@ -278,17 +289,17 @@ void build_cumulant(Method& m) {
 // ------------------------------------------------------------------ storage
 // Round to nearest, ties to even, keeping `bits` significant bits; below
 // 2^min_normal the spacing is fixed at 2^quantum (subnormals).
-double round_bits(double x, int bits, int min_normal, int quantum) {
+real round_bits(real x, int bits, int min_normal, int quantum) {
   if (x == 0.0 || !std::isfinite(x)) return x;
   if (std::fabs(x) < std::ldexp(1.0, min_normal)) return std::ldexp(std::nearbyint(std::ldexp(x, -quantum)), quantum);
   int e = 0;
-  const double mant = std::frexp(x, &e);   // x = mant 2^e, 0.5 <= |mant| < 1
+  const real mant = std::frexp(x, &e);   // x = mant 2^e, 0.5 <= |mant| < 1
   return std::ldexp(std::nearbyint(std::ldexp(mant, bits)), e - bits);
 }
 
-double round_storage(double x, int storage) {
+real round_storage(real x, int storage) {
   switch (storage) {
-    case 1: return (double)(float)x;                  // FP32 (IEEE conversion rounds to nearest even)
+    case 1: return (real)(float)x;                  // FP32 (IEEE conversion rounds to nearest even)
     case 2: return round_bits(x, 8, -126, -133);      // BF16
     case 3: return round_bits(x, 11, -14, -24);       // FP16
     default: return x;
@@ -298,35 +309,35 @@ double round_storage(double x, int storage) {
 // ------------------------------------------------------------------ one cell
 // Equilibrium, Eq. (3) at second order:
 // f^eq_q = w_q rho + w_q rho_0 [c.u / c_s^2 + (c.u)^2 / (2 c_s^4) - u.u / (2 c_s^2)].
-void equilibrium(const Lattice& L, double rho, const double u[3], double r0, double* feq) {
-  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+void equilibrium(const Lattice& L, real rho, const real u[3], real r0, real* feq) {
+  const real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int q = 0; q < L.Q; ++q) {
-    const double cu = L.c[q][0] * u[0] + L.c[q][1] * u[1] + L.c[q][2] * u[2];
+    const real cu = L.c[q][0] * u[0] + L.c[q][1] * u[1] + L.c[q][2] * u[2];
     feq[q] = L.w[q] * rho + L.w[q] * r0 * (cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2));
   }
 }
 
 // Guo's source without its rate factor:
 // S_q = w_q [(c_q - u).F / c_s^2 + (c_q.u)(c_q.F) / c_s^4].
-void guo(const Lattice& L, const double u[3], const double F[3], double* S) {
-  const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+void guo(const Lattice& L, const real u[3], const real F[3], real* S) {
+  const real uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
   for (int q = 0; q < L.Q; ++q) {
-    const double cu = L.c[q][0] * u[0] + L.c[q][1] * u[1] + L.c[q][2] * u[2];
-    const double cF = L.c[q][0] * F[0] + L.c[q][1] * F[1] + L.c[q][2] * F[2];
+    const real cu = L.c[q][0] * u[0] + L.c[q][1] * u[1] + L.c[q][2] * u[2];
+    const real cF = L.c[q][0] * F[0] + L.c[q][1] * F[1] + L.c[q][2] * F[2];
     S[q] = L.w[q] * ((cF - uF) / CS2 + cu * cF / (CS2 * CS2));
   }
 }
 
 // Eq. (2) with Guo's shift: rho = sum g, u = (sum c g + F/2) / rho_0.
-void macroscopic(const Method& m, const double* g, const double F[3], double& rho, double u[3]) {
+void macroscopic(const Method& m, const real* g, const real F[3], real& rho, real u[3]) {
   const Lattice& L = m.L;
   rho = 0;
-  double j[3] = {0, 0, 0};
+  real j[3] = {0, 0, 0};
   for (int q = 0; q < L.Q; ++q) {
     rho += g[q];
     for (int a = 0; a < 3; ++a) j[a] += L.c[q][a] * g[q];
   }
-  const double den = m.compressible ? rho : m.rho0;
+  const real den = m.compressible ? rho : m.rho0;
   for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / den;
 }
 
@@ -340,39 +351,39 @@ void macroscopic(const Method& m, const double* g, const double F[3], double& rh
 // moment map axis by axis: on each axis (f_-, f_0, f_+) -> (m_0, m_1, m_2) =
 // (f_- + f_0 + f_+, f_+ - f_-, f_+ + f_-), whose inverse is
 // f_- = (m_2 - m_1)/2, f_0 = m_0 - m_2, f_+ = (m_2 + m_1)/2.
-void collide_cumulant(const Method& m, const double* g, double* out) {
+void collide_cumulant(const Method& m, const real* g, real* out) {
   const Lattice& L = m.L;
   const int ne = (int)m.ex.size() / 3;
-  double mom[27], mu[27], kap[27], post[27], mup[27];
+  real mom[27], mu[27], kap[27], post[27], mup[27];
   for (int e = 0; e < ne; ++e) {
-    double s = 0;
+    real s = 0;
     for (int q = 0; q < L.Q; ++q)
       s += ipow(L.c[q][0], m.ex[3 * e]) * ipow(L.c[q][1], m.ex[3 * e + 1]) * ipow(L.c[q][2], m.ex[3 * e + 2]) * g[q];
     mom[e] = s;
   }
   const int e0 = ex_index(m, 0, 0, 0);
-  const double rho = mom[e0];
+  const real rho = mom[e0];
   for (int e = 0; e < ne; ++e) mu[e] = mom[e] / rho;
   for (int e = 0; e < ne; ++e) {
     if (e == e0) continue;
-    double tot = 0;
+    real tot = 0;
     for (const auto& blocks : m.parts[e]) {
       const int k = (int)blocks.size();
-      double fact = 1;
+      real fact = 1;
       for (int i = 2; i < k; ++i) fact *= i;     // (k - 1)!
-      double prod = ((k - 1) % 2 == 0 ? 1.0 : -1.0) * fact;
+      real prod = ((k - 1) % 2 == 0 ? 1.0 : -1.0) * fact;
       for (int b : blocks) prod *= mu[b];
       tot += prod;
     }
     kap[e] = tot;
   }
   const int D = L.d;
-  double tr = 0;
+  real tr = 0;
   for (int e = 0; e < ne; ++e) {
     const int a = m.ex[3 * e], b = m.ex[3 * e + 1], c = m.ex[3 * e + 2];
     if (a + b + c == 2 && std::max(a, std::max(b, c)) == 2) tr += kap[e];
   }
-  const double tr_post = tr + m.omega_bulk * (D * CS2 - tr);
+  const real tr_post = tr + m.omega_bulk * (D * CS2 - tr);
   for (int e = 0; e < ne; ++e) {
     if (e == e0) continue;
     const int a = m.ex[3 * e], b = m.ex[3 * e + 1], c = m.ex[3 * e + 2];
@@ -382,7 +393,7 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
     } else if (n == 2 && std::max(a, std::max(b, c)) == 1) {
       post[e] = kap[e] - m.omega * kap[e];
     } else if (n == 2) {
-      const double dev = kap[e] - tr / D;
+      const real dev = kap[e] - tr / D;
       post[e] = (1 - m.omega) * dev + tr_post / D;
     } else {
       post[e] = kap[e] - m.hi[n - 3] * kap[e];
@@ -393,9 +404,9 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
       mup[e] = 1.0;
       continue;
     }
-    double tot = 0;
+    real tot = 0;
     for (const auto& blocks : m.parts[e]) {
-      double prod = 1;
+      real prod = 1;
       for (int b : blocks) prod *= post[b];
       tot += prod;
     }
@@ -403,9 +414,9 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
   }
   // moments [a][b][c] -> populations [x][y][z] (index 0, 1, 2 = velocity -1, 0, +1)
   const int nz = L.d == 3 ? 3 : 1;
-  double A[3][3][3] = {}, B[3][3][3] = {};
+  real A[3][3][3] = {}, B[3][3][3] = {};
   for (int e = 0; e < ne; ++e) A[m.ex[3 * e]][m.ex[3 * e + 1]][m.ex[3 * e + 2]] = rho * mup[e];
-  auto inv1 = [](double m0, double m1, double m2, double* f) {
+  auto inv1 = [](real m0, real m1, real m2, real* f) {
     f[0] = 0.5 * (m2 - m1);
     f[1] = m0 - m2;
     f[2] = 0.5 * (m2 + m1);
@@ -413,7 +424,7 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
   if (nz == 3) {   // along z: A[a][b][c] -> B[a][b][vz]
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
-        double f[3];
+        real f[3];
         inv1(A[a][b][0], A[a][b][1], A[a][b][2], f);
         for (int v = 0; v < 3; ++v) B[a][b][v] = f[v];
       }
@@ -423,13 +434,13 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
   }
   for (int a = 0; a < 3; ++a)      // along y: B[a][b][vz] -> A[a][vy][vz]
     for (int v = 0; v < nz; ++v) {
-      double f[3];
+      real f[3];
       inv1(B[a][0][v], B[a][1][v], B[a][2][v], f);
       for (int k = 0; k < 3; ++k) A[a][k][v] = f[k];
     }
   for (int k = 0; k < 3; ++k)      // along x: A[a][vy][vz] -> B[vx][vy][vz]
     for (int v = 0; v < nz; ++v) {
-      double f[3];
+      real f[3];
       inv1(A[0][k][v], A[1][k][v], A[2][k][v], f);
       for (int i = 0; i < 3; ++i) B[i][k][v] = f[i];
     }
@@ -440,14 +451,14 @@ void collide_cumulant(const Method& m, const double* g, double* out) {
 }
 
 // Collision of one cell: pre-collision g -> post-collision out.
-void collide(const Method& m, const double* g, const double F[3], double* out) {
+void collide(const Method& m, const real* g, const real F[3], real* out) {
   const Lattice& L = m.L;
   const int Q = L.Q;
   if (m.method == CUMULANT) {
     collide_cumulant(m, g, out);
     return;
   }
-  double rho, u[3], feq[27], S[27];
+  real rho, u[3], feq[27], S[27];
   macroscopic(m, g, F, rho, u);
   equilibrium(L, rho, u, m.compressible ? rho : m.rho0, feq);
   guo(L, u, F, S);
@@ -457,19 +468,19 @@ void collide(const Method& m, const double* g, const double F[3], double* out) {
   } else if (m.method == TRT) {
     // even (symmetric) and odd (antisymmetric) parts of each (q, opp q) pair
     // relax with omega_e and omega_o; the source is split the same way
-    const double we = m.omega, wo = m.omega_odd;
+    const real we = m.omega, wo = m.omega_odd;
     for (int q = 0; q < Q; ++q) {
       const int o = L.opp[q];
-      const double gp = 0.5 * (g[q] + g[o]), gm = 0.5 * (g[q] - g[o]);
-      const double ep = 0.5 * (feq[q] + feq[o]), em = 0.5 * (feq[q] - feq[o]);
-      const double sp = 0.5 * (S[q] + S[o]), sm = 0.5 * (S[q] - S[o]);
+      const real gp = 0.5 * (g[q] + g[o]), gm = 0.5 * (g[q] - g[o]);
+      const real ep = 0.5 * (feq[q] + feq[o]), em = 0.5 * (feq[q] - feq[o]);
+      const real sp = 0.5 * (S[q] + S[o]), sm = 0.5 * (S[q] - S[o]);
       out[q] = g[q] - we * (gp - ep) - wo * (gm - em) + (1 - 0.5 * we) * sp + (1 - 0.5 * wo) * sm;
     }
   } else {
     // Eq. (4): f* = g - M^-1 S M (g - f^eq) + M^-1 (I - S/2) M S_Guo
-    double mneq[27], msrc[27];
+    real mneq[27], msrc[27];
     for (int k = 0; k < Q; ++k) {
-      double a = 0, b = 0;
+      real a = 0, b = 0;
       for (int q = 0; q < Q; ++q) {
         a += m.M[(size_t)k * Q + q] * (g[q] - feq[q]);
         b += m.M[(size_t)k * Q + q] * S[q];
@@ -478,7 +489,7 @@ void collide(const Method& m, const double* g, const double F[3], double* out) {
       msrc[k] = (1 - 0.5 * m.rate[k]) * b;
     }
     for (int q = 0; q < Q; ++q) {
-      double a = 0;
+      real a = 0;
       for (int k = 0; k < Q; ++k) a += m.Minv[(size_t)q * Q + k] * (msrc[k] - mneq[k]);
       out[q] = g[q] + a;
     }
@@ -507,8 +518,8 @@ extern "C" {
 typedef struct {
   int32_t stencil, method, storage, compressible;
   int32_t nx, ny, nz;
-  double omega, omega_bulk, omega_odd, magic, omega_hi[4];
-  double rho0;
+  real omega, omega_bulk, omega_odd, magic, omega_hi[4];
+  real rho0;
 } orc_config;
 
 }  // extern "C"
@@ -539,23 +550,23 @@ extern "C" {
 // P (Q*N) = f^eq(rho, u) (Eq. 3) at fluid cells, w_q rho_0 at solid cells,
 // then the storage rounding.  rho: N values or NULL (rho_0); u: 3*N values
 // (component-major) or NULL (rest); mask: N bytes (0 fluid) or NULL.
-int32_t orc_init(const orc_config* cfg, const uint8_t* mask, const double* rho, const double* u, double* P) {
+int32_t orc_init(const orc_config* cfg, const uint8_t* mask, const real* rho, const real* u, real* P) {
   Method m;
   if (!setup(cfg, m) || !P) return -1;
   const int64_t N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   const int Q = m.L.Q;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
-    double feq[27];
+    real feq[27];
     if (mask && mask[i]) {
       for (int q = 0; q < Q; ++q) feq[q] = m.L.w[q] * m.rho0;
     } else {
-      const double r = rho ? rho[i] : m.rho0;
-      const double uu[3] = {u ? u[i] : 0.0, u ? u[N + i] : 0.0, u ? u[2 * N + i] : 0.0};
+      const real r = rho ? rho[i] : m.rho0;
+      const real uu[3] = {u ? u[i] : 0.0, u ? u[N + i] : 0.0, u ? u[2 * N + i] : 0.0};
       equilibrium(m.L, r, uu, m.compressible ? r : m.rho0, feq);
     }
     for (int q = 0; q < Q; ++q) {
-      const double sh = m.L.w[q] * m.rho0;
+      const real sh = m.L.w[q] * m.rho0;
       P[q * N + i] = m.storage ? round_storage(feq[q] - sh, m.storage) + sh : feq[q];
     }
   }
@@ -566,7 +577,7 @@ int32_t orc_init(const orc_config* cfg, const uint8_t* mask, const double* rho, 
 // force_y: 3*ny doubles, force of row y at [3*y + a], or NULL (no force);
 // wall_u: 3*128 doubles, velocity of wall type k at [3*k + a], or NULL (all
 // walls at rest); nthreads <= 0: all available.
-int32_t orc_run(const orc_config* cfg, const uint8_t* mask, const double* force_y, const double* wall_u, double* P,
+int32_t orc_run(const orc_config* cfg, const uint8_t* mask, const real* force_y, const real* wall_u, real* P,
                 int32_t nsteps, int32_t nthreads) {
   Method m;
   if (!setup(cfg, m) || !P || nsteps < 0) return -1;
@@ -574,16 +585,16 @@ int32_t orc_run(const orc_config* cfg, const uint8_t* mask, const double* force_
   const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
   const int64_t N = (int64_t)nx * ny * nz;
   const int Q = m.L.Q;
-  std::vector<double> other((size_t)Q * N);
-  double* src = P;
-  double* dst = other.data();
+  std::vector<real> other((size_t)Q * N);
+  real* src = P;
+  real* dst = other.data();
   const int nt = nthreads_of(nthreads);
   for (int t = 0; t < nsteps; ++t) {
 #pragma omp parallel for collapse(2) schedule(static) num_threads(nt)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y) {
-        double g[27], out[27];
-        const double F[3] = {force_y ? force_y[3 * y] : 0.0, force_y ? force_y[3 * y + 1] : 0.0,
+        real g[27], out[27];
+        const real F[3] = {force_y ? force_y[3 * y] : 0.0, force_y ? force_y[3 * y + 1] : 0.0,
                              force_y ? force_y[3 * y + 2] : 0.0};
         for (int x = 0; x < nx; ++x) {
           const int64_t i = ((int64_t)z * ny + y) * nx + x;
@@ -597,7 +608,7 @@ int32_t orc_run(const orc_config* cfg, const uint8_t* mask, const double* force_
             const int zs = wrap(z - m.L.c[q][2], nz);
             const int64_t s = ((int64_t)zs * ny + ys) * nx + xs;
             if (mask && mask[s]) {
-              double cu = 0;
+              real cu = 0;
               if (wall_u)
                 for (int a = 0; a < 3; ++a) cu += m.L.c[q][a] * wall_u[3 * mask[s] + a];
               g[q] = src[m.L.opp[q] * N + i] + 2 * m.L.w[q] * m.rho0 * cu / CS2;
@@ -607,22 +618,22 @@ int32_t orc_run(const orc_config* cfg, const uint8_t* mask, const double* force_
           }
           collide(m, g, F, out);
           for (int q = 0; q < Q; ++q) {
-            const double sh = m.L.w[q] * m.rho0;
+            const real sh = m.L.w[q] * m.rho0;
             dst[q * N + i] = m.storage ? round_storage(out[q] - sh, m.storage) + sh : out[q];
           }
         }
       }
     std::swap(src, dst);
   }
-  if (src != P) std::memcpy(P, src, sizeof(double) * (size_t)Q * N);
+  if (src != P) std::memcpy(P, src, sizeof(real) * (size_t)Q * N);
   return 0;
 }
 
 // Readout of the stored post-collision state: rho = sum P,
 // u = (sum c P - F/2) / rho_0 (rho_0 = rho when compressible); solid cells
 // read rho = u = 0.  rho: N or NULL, u: 3*N or NULL.
-int32_t orc_readout(const orc_config* cfg, const uint8_t* mask, const double* force_y, const double* P, double* rho,
-                    double* u) {
+int32_t orc_readout(const orc_config* cfg, const uint8_t* mask, const real* force_y, const real* P, real* rho,
+                    real* u) {
   Method m;
   if (!setup(cfg, m) || !P) return -1;
   const int nx = cfg->nx, ny = cfg->ny;
@@ -631,17 +642,17 @@ int32_t orc_readout(const orc_config* cfg, const uint8_t* mask, const double* fo
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
     const int y = (int)((i / nx) % ny);
-    double r = 0, j[3] = {0, 0, 0};
+    real r = 0, j[3] = {0, 0, 0};
     for (int q = 0; q < Q; ++q) {
       r += P[q * N + i];
       for (int a = 0; a < 3; ++a) j[a] += m.L.c[q][a] * P[q * N + i];
     }
     const bool solid = mask && mask[i];
-    const double den = m.compressible ? r : m.rho0;
+    const real den = m.compressible ? r : m.rho0;
     if (rho) rho[i] = solid ? 0.0 : r;
     if (u)
       for (int a = 0; a < 3; ++a) {
-        const double F = force_y ? force_y[3 * y + a] : 0.0;
+        const real F = force_y ? force_y[3 * y + a] : 0.0;
         u[a * N + i] = solid ? 0.0 : (j[a] - 0.5 * F) / den;
       }
   }
@@ -649,17 +660,17 @@ int32_t orc_readout(const orc_config* cfg, const uint8_t* mask, const double* fo
 }
 
 // Totals over fluid cells: out = (sum rho, sum j_x, sum j_y, sum j_z).
-int32_t orc_conserved(const orc_config* cfg, const uint8_t* mask, const double* P, double* out) {
+int32_t orc_conserved(const orc_config* cfg, const uint8_t* mask, const real* P, real* out) {
   Method m;
   if (!setup(cfg, m) || !P || !out) return -1;
   const int64_t N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   const int Q = m.L.Q;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  real s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma omp parallel for schedule(static) reduction(+ : s0, s1, s2, s3)
   for (int64_t i = 0; i < N; ++i) {
     if (mask && mask[i]) continue;
     for (int q = 0; q < Q; ++q) {
-      const double v = P[q * N + i];
+      const real v = P[q * N + i];
       s0 += v;
       s1 += m.L.c[q][0] * v;
       s2 += m.L.c[q][1] * v;
@@ -675,10 +686,10 @@ int32_t orc_conserved(const orc_config* cfg, const uint8_t* mask, const double* 
 
 // One collision of `n` independent cells: g (Q*n, cell-major: g[c*Q + q]) ->
 // out (same layout); F: 3 doubles or NULL.  For single-cell pins.
-int32_t orc_collide_cells(const orc_config* cfg, const double* g, const double* F, int64_t n, double* out) {
+int32_t orc_collide_cells(const orc_config* cfg, const real* g, const real* F, int64_t n, real* out) {
   Method m;
   if (!setup(cfg, m) || !g || !out) return -1;
-  const double F0[3] = {F ? F[0] : 0.0, F ? F[1] : 0.0, F ? F[2] : 0.0};
+  const real F0[3] = {F ? F[0] : 0.0, F ? F[1] : 0.0, F ? F[2] : 0.0};
   if (m.method == CUMULANT && F && (F[0] != 0 || F[1] != 0 || F[2] != 0)) return -2;
   const int Q = m.L.Q;
   for (int64_t c = 0; c < n; ++c) collide(m, g + c * Q, F0, out + c * Q);
@@ -686,13 +697,13 @@ int32_t orc_collide_cells(const orc_config* cfg, const double* g, const double* 
 }
 
 // MRT basis of the stencil (rows M[k][q]) and its per-row rates, for pins.
-int32_t orc_mrt_basis(const orc_config* cfg, double* M, double* rate) {
+int32_t orc_mrt_basis(const orc_config* cfg, real* M, real* rate) {
   Method m;
   orc_config c = *cfg;
   c.method = MRT;
   if (!setup(&c, m) || !M || !rate) return -1;
-  std::memcpy(M, m.M.data(), sizeof(double) * m.M.size());
-  std::memcpy(rate, m.rate.data(), sizeof(double) * m.rate.size());
+  std::memcpy(M, m.M.data(), sizeof(real) * m.M.size());
+  std::memcpy(rate, m.rate.data(), sizeof(real) * m.rate.size());
   return 0;
 }
 

@@ -392,14 +392,13 @@ __global__ __launch_bounds__(256) void k_copy_generic(const E* __restrict__ src,
   for (int q = 0; q < Q; ++q) dst[q * n + i] = src[q * n + i];
 }
 
-// The copy reference runs in the launch shape of the D3Q19 sweeps on
-// streaming sizes: 12 waves per CU for 8-byte elements, 16 for 4-byte
-// elements, full occupancy for 2-byte elements.
+// The copy reference runs with the occupancy the caller names (the launch
+// shape of the sweep it is compared with): at most waves_per_cu wavefronts
+// per CU, 0 = full occupancy.
 template <class E>
-hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, hipStream_t s) {
+hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, int waves_per_cu, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const bool stream = (size_t)n * (size_t)q * sizeof(E) > kStreamGridBytes;
-  const unsigned lds = !stream ? 0u : occupancy_lds(sizeof(E) == 8 ? 12 : (sizeof(E) == 4 ? 16 : 0), 256);
+  const unsigned lds = occupancy_lds(waves_per_cu, 256);
   switch (q) {
     case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
     case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
@@ -425,11 +424,12 @@ unsigned occupancy_lds(int waves_per_cu, int block_threads) {
   return lds_per_cu[dev] / lds == blocks ? (unsigned)lds : 0u;
 }
 
-hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, hipStream_t s) {
+hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, int waves_per_cu,
+                         hipStream_t s) {
   switch (elem_bytes) {
-    case 2: return copy_q_typed<uint16_t>(src, dst, n, q, s);
-    case 4: return copy_q_typed<uint32_t>(src, dst, n, q, s);
-    case 8: return copy_q_typed<uint64_t>(src, dst, n, q, s);
+    case 2: return copy_q_typed<uint16_t>(src, dst, n, q, waves_per_cu, s);
+    case 4: return copy_q_typed<uint32_t>(src, dst, n, q, waves_per_cu, s);
+    case 8: return copy_q_typed<uint64_t>(src, dst, n, q, waves_per_cu, s);
   }
   return hipErrorInvalidValue;
 }

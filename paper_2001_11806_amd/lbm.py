@@ -60,7 +60,7 @@ SIGNATURES = {
     "lbm_adjoint_seed": ([_P, _P, _P, _I32], _I32),
     "lbm_adjoint_step": ([_P, _I32], _I32),
     "lbm_adjoint_grads": ([_P, _P, _P, _I32, _DP], _I32),
-    "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _P], _I32),
+    "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _P], _I32),
     "lbm_last_error": ([], ctypes.c_char_p),
     "lbm_version": ([], _I32),
 }
@@ -287,8 +287,9 @@ class LBM:
         return du, dr, np.array(list(dF))
 
 
-def copy_q(src, dst, n, q, elem_bytes, stream):
-    """Q-stream copy bandwidth reference (see include/lbm.h)."""
+def copy_q(src, dst, n, q, elem_bytes, stream, waves_per_cu=0):
+    """Q-stream copy bandwidth reference (see include/lbm.h); waves_per_cu
+    0 = full occupancy."""
     lib = load_library()
-    _check(lib.lbm_copy_q(_ptr(src), _ptr(dst), int(n), int(q), int(elem_bytes),
+    _check(lib.lbm_copy_q(_ptr(src), _ptr(dst), int(n), int(q), int(elem_bytes), int(waves_per_cu),
                           ctypes.c_void_p(stream.cuda_stream)))

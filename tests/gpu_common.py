@@ -64,4 +64,8 @@ def ulp_of(x, dtype):
 
 
 def rel_l2(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+    """||a - b|| / ||b||; the difference is taken in the wider of the two
+    floating types (long double references keep their extra bits)."""
+    t = np.result_type(np.asarray(a).dtype, np.asarray(b).dtype, np.float64)
+    d = (np.asarray(a, dtype=t) - np.asarray(b, dtype=t)).astype(np.float64)
+    return float(np.linalg.norm(d.ravel()) / max(np.linalg.norm(np.asarray(b, dtype=np.float64).ravel()), 1e-300))

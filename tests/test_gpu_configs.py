@@ -200,16 +200,18 @@ def test_c2_channel_streaming_size_200_steps_f64_vs_oracle():
     along x, u noise 1e-3, seed 2) on a 128 x 256 x 128 channel: 638 MB per
     FP64 grid, above the 512 MiB bound past which the sweep streams with
     non-temporal stores in the plain block order, as at 256^3.  All 200
-    steps against the C++ FP64 oracle: every stored population within 1e-13,
-    relative L2 of u and of rho - 1 within 1e-12."""
+    steps against the C++ oracle computed in long double (the FP64 oracle's
+    own rounding moves u by 3.7e-12 and rho - 1 by 2.4e-9 here,
+    ``tests/golden/fp64_oracle_floor.txt``): every stored population within
+    1e-13, relative L2 of u and of rho - 1 within 1e-12."""
     need_gpu()
     dims = (128, 256, 128)
     T = 200
     mask, _, u = inputs.channel_flow(256, seed=2, amp=1e-3, nx=128, nz=128)
     F = np.array([1e-6, 0.0, 0.0])
     cfg = orun.Config("D3Q19", "TRT", TRT)
-    P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, None, u, mask), T, mask, F)
-    ro, uo = ocpu.readout(cfg, P, mask, F)
+    P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, None, u, mask, precision="ld"), T, mask, F, precision="ld")
+    ro, uo = ocpu.readout(cfg, P, mask, F, precision="ld")
     g = make_gpu("D3Q19", "TRT", "f64", dims, mask, TRT)
     assert g.Q * g.N * 8 > 512 * 2 ** 20
     g.set_force(F)
@@ -219,9 +221,10 @@ def test_c2_channel_streaming_size_200_steps_f64_vs_oracle():
     Pg = to_np(g.get_pdfs())
     g.close()
     fl = mask == 0
-    dP = float(np.max(np.abs(Pg - P)))
+    dP = float(np.max(np.abs((Pg - P).astype(np.float64))))
     eu, er = rel_l2(ug, uo), rel_l2(rg[fl] - 1, ro[fl] - 1)
-    print("C2 128x256x128 x %d f64 vs C++ oracle: max |dP| %.2e, rel L2 u %.2e, rho-1 %.2e" % (T, dP, eu, er))
+    print("C2 128x256x128 x %d f64 vs long double oracle: max |dP| %.2e, rel L2 u %.2e, rho-1 %.2e"
+          % (T, dP, eu, er))
     assert dP <= 1e-13 and eu <= 1e-12 and er <= 1e-12
 
 
@@ -247,30 +250,33 @@ _C3_REF = {}
 
 
 def _c3_reference(n, times):
-    """FP64 C++ oracle trajectory of the C3 recipe on an n^3 box (cached)."""
+    """Long double C++ oracle trajectory of the C3 recipe on an n^3 box
+    (cached): the readouts at each of ``times``."""
     key = (n, times)
     if key not in _C3_REF:
         u = inputs.solenoidal_velocity(n, inputs.solenoidal_modes(seed=3))
         cfg = orun.Config("D3Q27", "CUMULANT", CUM)
-        P = ocpu.init_equilibrium(cfg, None, u)
+        P = ocpu.init_equilibrium(cfg, None, u, precision="ld")
         snaps, t = {}, 0
         for T in times:
-            P = ocpu.run(cfg, P, T - t)
+            P = ocpu.run(cfg, P, T - t, precision="ld")
             t = T
-            snaps[T] = ocpu.readout(cfg, P)
+            snaps[T] = ocpu.readout(cfg, P, precision="ld")
         _C3_REF[key] = (u, snaps)
     return _C3_REF[key]
 
 
 def test_c3_cumulant_reduced_multistep_errors():
     """The C3 recipe on a 48^3 box at its configured 500 steps (and at 100),
-    every storage type against the plain FP64 C++ oracle, relative L2 of u
-    and of rho - 1.  Bars: FP64 1e-12; FP32 1e-5 for u, 5e-5 for rho - 1
-    (|rho - 1| is about 1e-3, so that is 5e-8 of rho); 16-bit: three times
-    the error that the storage rounding alone causes in the same run (the
-    oracle with emulated rounding, ``tests/golden/c3_storage_floor.txt``).
-    FP32 storage alone gives 2e-8 in u, so the FP32 bar tests the kernel's
-    arithmetic, not its storage."""
+    every storage type against the C++ oracle in long double (the FP64
+    oracle's own rounding moves rho - 1 by up to 2e-12 here,
+    ``tests/golden/fp64_oracle_floor.txt``), relative L2 of u and of rho - 1.
+    Bars: FP64 1e-12; FP32 1e-5 for u, 5e-5 for rho - 1 (|rho - 1| is about
+    1e-3, so that is 5e-8 of rho); 16-bit: three times the error that the
+    storage rounding alone causes in the same run (the oracle with emulated
+    rounding, ``tests/golden/c3_storage_floor.txt``).  FP32 storage alone
+    gives 2e-8 in u, so the FP32 bar tests the kernel's arithmetic, not its
+    storage."""
     need_gpu()
     from tests.golden.c3_storage_floor import read_floor
     floor = read_floor()

@@ -247,6 +247,31 @@ def test_mrt_all_rates_equal_is_srt(name):
             np.testing.assert_allclose(a, b, rtol=0, atol=2e-15)
 
 
+@pytest.mark.parametrize("name", STENCILS)
+def test_mrt_even_odd_rates_is_trt(name):
+    """Pins which moment order each higher-order rate acts on: MRT with the
+    even rate on the shear, bulk, order-4 and order-6 groups and the odd rate
+    on orders 3 and 5 is TRT(even, odd) (Sec. III-C "SRT, TRT" and "MRT":
+    even-order polynomials are symmetric in c, odd-order ones antisymmetric,
+    and the weighted Gram-Schmidt never mixes the two).  Negative control:
+    the order-3 and order-4 rates swapped is not TRT."""
+    lat = lattice.velocity_set(name)
+    rng = np.random.default_rng(18)
+    f = _random_pdfs(lat, 11, rng)
+    F = 1e-4 * rng.standard_normal((3, 11))
+    if lat.d == 2:
+        F[2] = 0
+    we, wo = 1.37, 1.81
+    trt = dict(RATES, omega=we, omega_odd=wo)
+    mrt = dict(RATES, omega=we, omega_bulk=we, omega_hi=(wo, we, wo, we))
+    for force in (None, F):
+        a = collision.mrt(lat, f, mrt, force)
+        b = collision.trt(lat, f, trt, force)
+        np.testing.assert_allclose(a, b, rtol=0, atol=2e-15)
+    swapped = dict(mrt, omega_hi=(we, wo, wo, we))
+    assert np.max(np.abs(collision.mrt(lat, f, swapped) - collision.trt(lat, f, trt))) > 1e-6
+
+
 @pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
 def test_trt_population_form_equals_paper_moment_form(name):
     """The +/- population TRT equals the paper's TRT built from raw

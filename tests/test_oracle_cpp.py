@@ -200,6 +200,23 @@ def test_cpp_mrt_basis_weighted_orthogonal_and_equal_rates_give_srt(stencil):
     np.testing.assert_allclose(cpu.collide_cells(cfg, g, F), cpu.collide_cells(srt, g, F), rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+def test_cpp_mrt_even_odd_rates_is_trt(stencil):
+    """MRT with the even rate on shear, bulk, orders 4 and 6 and the odd rate
+    on orders 3 and 5 equals TRT(even, odd) (Sec. III-C "SRT, TRT", "MRT"):
+    pins the C++ oracle's mapping of the higher-order rates to moment orders.
+    Negative control: order-3 and order-4 rates swapped."""
+    we, wo = 1.37, 1.81
+    mrt = orun.Config(stencil, "MRT", dict(RATES, omega=we, omega_bulk=we, omega_hi=(wo, we, wo, we)))
+    trt = orun.Config(stencil, "TRT", dict(RATES, omega=we, omega_odd=wo))
+    rng = np.random.default_rng(19)
+    g = mrt.lat.w[:, None] * (1 + 0.05 * rng.standard_normal((mrt.lat.Q, 40)))
+    F = np.array([1e-4, 2e-4, 0.0 if stencil == "D2Q9" else -1e-4])
+    np.testing.assert_allclose(cpu.collide_cells(mrt, g, F), cpu.collide_cells(trt, g, F), rtol=0, atol=2e-15)
+    bad = orun.Config(stencil, "MRT", dict(RATES, omega=we, omega_bulk=we, omega_hi=(we, wo, wo, we)))
+    assert np.max(np.abs(cpu.collide_cells(bad, g, F) - cpu.collide_cells(trt, g, F))) > 1e-6
+
+
 def test_cpp_poiseuille_trt_magic_exact_and_srt_slip():
     """Steady Poiseuille between halfway walls: exact with TRT, Lambda = 3/16
     (Ginzburg's result); SRT at tau = 0.8 slips (negative control)."""
@@ -291,3 +308,32 @@ def test_cpp_storage_rounding_matches_numpy_casts():
         np.testing.assert_array_equal(dev, orun.round_storage(dev, storage))
         P64 = orun.init_equilibrium(orun.Config("D3Q19", "SRT", dict(omega=1.0)), np.ones(u.shape[1:]), u)
         np.testing.assert_array_equal(P, orun.quantize(cfg, P64))
+
+
+@pytest.mark.parametrize("stencil,method", CASES)
+def test_cpp_long_double_build_is_the_same_method(stencil, method):
+    """The long double build (the reference of the FP64 GPU parity tests) is
+    the same method: from the same rounded FP64 state, five steps agree with
+    the FP64 build to the FP64 rounding of the state (1e-14), and with the
+    numpy oracle run on np.longdouble arrays (exact-rational weights) to
+    1e-16, well below FP64 rounding.  (The numpy run keeps c_s^2 as the
+    float64 1/3, a 2e-17 relative difference.)"""
+    dims = (23, 7, 1) if stencil == "D2Q9" else (23, 7, 5)
+    cum = method == "CUMULANT"
+    mask, rho, u = _fields(stencil, dims, 7, with_mask=not cum)
+    rates = GEN if cum else RATES
+    F = None if cum else np.array([2e-4, -1e-4, 0.0 if stencil == "D2Q9" else 5e-5])
+    cfg = orun.Config(stencil, method, rates)
+    P0 = cpu.init_equilibrium(cfg, rho, u, mask)
+    P64 = cpu.run(cfg, P0, 5, mask, F)
+    Pld = cpu.run(cfg, P0, 5, mask, F, precision="ld")
+    assert Pld.dtype == np.longdouble
+    assert np.max(np.abs((P64 - Pld).astype(np.float64))) < 1e-14
+    assert np.max(np.abs((P64 - Pld).astype(np.float64))) > 0          # really another precision
+    if method != "CUMULANT":                                           # numpy cumulant inverts by LAPACK (no long double)
+        ld = np.longdouble
+        lcfg = orun.Config(stencil, method, rates)
+        lcfg.lat = lcfg.lat._replace(w=np.array([ld(f.numerator) / ld(f.denominator) for f in lcfg.lat.wf]))
+        Ff = None if F is None else orun.force_field(F, dims).astype(ld)
+        Pn = orun.run(lcfg, P0.astype(ld), 5, mask, Ff)
+        assert np.max(np.abs((Pn - Pld).astype(np.float64))) < 1e-16
