@@ -10,7 +10,12 @@ run of the same workload, the Q-stream copy reference, the D3Q27 cumulant
 (128^3, FP32, tape every 20 steps) and the D3Q27 MRT (512^3, FP16 vs FP64).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                       [--no-cpu-baseline]
+                       [--no-cpu-baseline] [--only fp32,aa,copy,methods,c1,c3,c4,c5]
+       python bench.py trace-summary DIR      (rocprofv3 --kernel-trace output,
+                                                per kernel and grid size)
+       python bench.py pmc-summary FETCH_DIR WRITE_DIR [--write]
+                                              (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+                                               runs; --write updates profiles/)
 """
 
 import argparse
@@ -122,6 +127,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--short", action="store_true",
+                    help="profiling runs: C3 and C5 for 20 steps instead of their configured 500 and 1000 "
+                         "(their error figures then refer to 20 steps)")
     ap.add_argument("--only", default="", help="comma list of extras to run (fp32,aa,copy,methods,c1,c3,c4,c5)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -184,24 +192,25 @@ def main():
         # the full 500-step run in every storage type; FP64 on the same GPU
         # (parity-checked against the oracle) is the reference for the errors
         n3 = 384
-        log("C3 D3Q27 cumulant 384^3, 500 steps: building solenoidal field")
+        T3 = 20 if args.short else 500
+        log("C3 D3Q27 cumulant 384^3, %d steps: building solenoidal field" % T3)
         modes = inputs.solenoidal_modes(seed=3)
         u3 = inputs.solenoidal_velocity(n3, modes, dtype=np.float32)
         cum = dict(omega=1 / 0.55, omega_bulk=1.0, omega_hi=(1.0,) * 4)
         ref = None
         for dt in ("f64", "f32", "bf16", "f16"):
             r = run_forward(torch, LBM, inputs, "D3Q27", "CUMULANT", dt, (n3, n3, n3), cum, None, u3,
-                            steps=495, warmup=5)
+                            steps=T3 - 5, warmup=5)
             uo, ro = r.pop("u_out"), r.pop("rho_out")
             if ref is None:
                 ref = (uo, ro)
             else:
-                r["rel_l2_u_vs_f64_500_steps"] = float((uo - ref[0]).norm() / ref[0].norm())
-                r["rel_l2_rho_minus_1_vs_f64_500_steps"] = float((ro - ref[1]).norm() / (ref[1] - 1).norm())
+                r["rel_l2_u_vs_f64_%d_steps" % T3] = float((uo - ref[0]).norm() / ref[0].norm())
+                r["rel_l2_rho_minus_1_vs_f64_%d_steps" % T3] = float((ro - ref[1]).norm() / (ref[1] - 1).norm())
             extras["c3_d3q27_cumulant_384_%s" % dt] = r
             log("  %s: %.0f MLUPS, %.0f GB/s%s" % (dt, r["mlups"], r["achieved_GBps"], "" if dt == "f64" else
-                ", rel L2 vs FP64: u %.2e, rho-1 %.2e" % (r["rel_l2_u_vs_f64_500_steps"],
-                                                          r["rel_l2_rho_minus_1_vs_f64_500_steps"])))
+                ", rel L2 vs FP64: u %.2e, rho-1 %.2e" % (r["rel_l2_u_vs_f64_%d_steps" % T3],
+                                                          r["rel_l2_rho_minus_1_vs_f64_%d_steps" % T3])))
             del uo, ro
             torch.cuda.empty_cache()
         del ref, u3
@@ -222,22 +231,23 @@ def main():
 
     if want("c5"):
         n5 = 512
-        log("C5 D3Q27 MRT 512^3, 1000 steps: building noise field")
+        T5 = 20 if args.short else 1000
+        log("C5 D3Q27 MRT 512^3, %d steps: building noise field" % T5)
         u5 = inputs.uniform_noise_velocity((n5, n5, n5), 1e-3, 5, None, dtype=np.float32)
         prof = inputs.kolmogorov_force_profile(n5, 1e-6)
         mrt = dict(omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.0,) * 4)
         ref = None
         for dt in ("f64", "f16"):
             r = run_forward(torch, LBM, inputs, "D3Q27", "MRT", dt, (n5, n5, n5), mrt, None, u5, profile=prof,
-                            steps=995, warmup=5)
+                            steps=T5 - 5, warmup=5)
             uo, ro = r.pop("u_out"), r.pop("rho_out")
             if ref is None:
                 ref = uo
             else:
-                r["rel_l2_u_vs_f64_same_gpu_1000_steps"] = float((uo - ref).norm() / ref.norm())
+                r["rel_l2_u_vs_f64_same_gpu_%d_steps" % T5] = float((uo - ref).norm() / ref.norm())
             extras["c5_d3q27_mrt_512_%s" % dt] = r
             log("  %s: %.0f MLUPS, %.0f GB/s%s" % (dt, r["mlups"], r["achieved_GBps"], "" if dt == "f64" else
-                ", rel L2 u vs FP64 after 1000 steps %.2e" % r["rel_l2_u_vs_f64_same_gpu_1000_steps"]))
+                ", rel L2 u vs FP64 after %d steps %.2e" % (T5, r["rel_l2_u_vs_f64_same_gpu_%d_steps" % T5])))
             del uo, ro
             torch.cuda.empty_cache()
         del ref, u5
@@ -530,5 +540,157 @@ def cpu_baseline(inputs):
             "host": host, "samples": samples}
 
 
+# ---------------------------------------------------------------- profile summaries
+# Counter summaries the benchmark reads back (MATCH): file -> (kernel symbol
+# as rocprofv3 names it, dispatch grid size in threads, algorithmic bytes per
+# launch, description).  C2: fluid = 256^3 - 2 * 256^2 cells plus one flag
+# byte per cell; C3 / C5 are periodic (no flags).
+_C2_FLUID = 256 ** 3 - 2 * 256 ** 2
+PROFILED = {
+    "sweep_d3q19_trt_256_f64_traffic.txt": (
+        "k_sweep<D3Q19, TRT, double, NT>", 256 ** 3, 2 * 19 * 8 * _C2_FLUID + 256 ** 3,
+        "k_sweep<D3Q19, TRT, double> on the 256^3 channel (C2 FP64, two arrays)"),
+    "sweep_d3q19_trt_256_f32_traffic.txt": (
+        "k_sweep<D3Q19, TRT, float, NT>", 256 ** 3, 2 * 19 * 4 * _C2_FLUID + 256 ** 3,
+        "k_sweep<D3Q19, TRT, float> on the 256^3 channel (C2 FP32-shifted, two arrays)"),
+    "sweep_aa_d3q19_trt_256_f64_traffic.txt": (
+        "k_sweep_aa_*<D3Q19, TRT, double, NT>", 256 ** 3, 2 * 19 * 8 * _C2_FLUID + 256 ** 3,
+        "k_sweep_aa_even / k_sweep_aa_odd<D3Q19, TRT, double> on the 256^3 channel (C2 FP64, AA), "
+        "averaged over both kernels"),
+    "sweep_d3q27_cumulant_384_f64_traffic.txt": (
+        "k_sweep<D3Q27, CUMULANT, double, NT>", 384 ** 3, 2 * 27 * 8 * 384 ** 3,
+        "k_sweep<D3Q27, CUMULANT, double> on the 384^3 periodic box (C3 FP64 reference)"),
+    "sweep_d3q27_cumulant_384_f32_traffic.txt": (
+        "k_sweep<D3Q27, CUMULANT, float, NT>", 384 ** 3, 2 * 27 * 4 * 384 ** 3,
+        "k_sweep<D3Q27, CUMULANT, float> on the 384^3 periodic box (C3 FP32)"),
+    "sweep_d3q27_cumulant_384_bf16_traffic.txt": (
+        "k_sweep<D3Q27, CUMULANT, bf16, NT>", 384 ** 3, 2 * 27 * 2 * 384 ** 3,
+        "k_sweep<D3Q27, CUMULANT, bf16> on the 384^3 periodic box (C3 BF16)"),
+    "sweep_d3q27_cumulant_384_f16_traffic.txt": (
+        "k_sweep<D3Q27, CUMULANT, f16, NT>", 384 ** 3, 2 * 27 * 2 * 384 ** 3,
+        "k_sweep<D3Q27, CUMULANT, f16> on the 384^3 periodic box (C3 FP16)"),
+    "sweep_d3q27_mrt_512_f64_traffic.txt": (
+        "k_sweep<D3Q27, MRT, double, NT>", 512 ** 3, 2 * 27 * 8 * 512 ** 3,
+        "k_sweep<D3Q27, MRT, double> on the 512^3 periodic box (C5 FP64)"),
+    "sweep_d3q27_mrt_512_f16_traffic.txt": (
+        "k_sweep<D3Q27, MRT, f16, NT>", 512 ** 3, 2 * 27 * 2 * 512 ** 3,
+        "k_sweep<D3Q27, MRT, f16> on the 512^3 periodic box (C5 FP16)"),
+}
+
+
+def _csv_rows(directory, suffix):
+    """Rows (dicts) of every rocprofv3 CSV named *<suffix> below directory."""
+    import csv
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    raise KeyError(names)
+
+
+def _kernel(row):
+    name = _col(row, "Kernel_Name", "Kernel-Name", "KernelName")
+    return name.replace("lbm::", "").replace("(anonymous namespace)::", "")
+
+
+def _grid(row):
+    try:
+        return int(_col(row, "Grid_Size", "Grid_Size_X", "Grid-Size"))
+    except KeyError:
+        return -1
+
+
+def trace_summary(directory):
+    """Per (kernel, grid size) statistics of a rocprofv3 --kernel-trace run:
+    calls, average / min / max duration in ns, workgroup size, VGPRs."""
+    groups = {}
+    for r in _csv_rows(directory, "kernel_trace.csv"):
+        d = int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))
+        key = (_kernel(r), _grid(r))
+        g = groups.setdefault(key, {"d": [], "wg": _col(r, "Workgroup_Size", "Workgroup_Size_X"),
+                                    "vgpr": r.get("Arch_VGPR_Count", r.get("VGPR_Count", "?"))})
+        g["d"].append(d)
+    lines = [" calls       avg_ns       min_ns       max_ns        grid    wg  vgpr  kernel"]
+    for (k, grid), g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"])):
+        d = g["d"]
+        lines.append("%6d %12.0f %12d %12d %11d %5s %5s  %s" % (len(d), sum(d) / len(d), min(d), max(d), grid,
+                                                             g["wg"], g["vgpr"], k))
+    return "\n".join(lines)
+
+
+def _counter_means(directory, counter):
+    acc = {}
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        key = (_kernel(r), _grid(r))
+        acc.setdefault(key, []).append(float(_col(r, "Counter_Value")))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def _copy_bytes(kernel, grid):
+    """Bytes one k_copy_q<E, Q> dispatch reads (and writes) over `grid` cells."""
+    import re
+    m = re.match(r"k_copy_q<uint(\d+), (\d+)>", kernel)
+    return None if not m else int(m.group(1)) // 8 * int(m.group(2)) * grid
+
+
+def pmc_summary(fetch_dir, write_dir, write_files=False):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of two rocprofv3 --pmc runs,
+    scaled by what the same counters read for the plain copy kernels of known
+    size in the same runs; with write_files, the summaries of PROFILED."""
+    fetch, write = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
+    fs, ws = [], []
+    for key in fetch:
+        b = _copy_bytes(*key)
+        if b and key in write:
+            fs.append(b / 1024 / fetch[key])
+            ws.append(b / 1024 / write[key])
+    if not fs:
+        raise SystemExit("no k_copy_q dispatch in the counter runs: nothing to calibrate with")
+    f_scale, w_scale = sum(fs) / len(fs), sum(ws) / len(ws)
+    out = ["# scale factors from %d copy kernels: fetch %.4f (spread %.4f..%.4f), write %.4f (%.4f..%.4f)"
+           % (len(fs), f_scale, min(fs), max(fs), w_scale, min(ws), max(ws)),
+           "  fetch_KiB     write_KiB       grid  kernel"]
+    for key in sorted(fetch, key=lambda k: -(fetch[k] + write.get(k, 0))):
+        out.append("%11.1f %13.1f %10d  %s" % (fetch[key], write.get(key, float("nan")), key[1], key[0]))
+    if write_files:
+        import fnmatch
+        for fname, (kern, grid, alg, desc) in PROFILED.items():
+            keys = [k for k in fetch if fnmatch.fnmatchcase(k[0], kern) and k[1] == grid and k in write]
+            if not keys:
+                out.append("# %s: kernel %s (grid %d) not in the runs" % (fname, kern, grid))
+                continue
+            fk = sum(fetch[k] for k in keys) / len(keys)
+            wk = sum(write[k] for k in keys) / len(keys)
+            hbm = (fk * f_scale + wk * w_scale) * 1024
+            with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
+                fh.write("# HBM traffic of %s (one launch)\n" % desc)
+                fh.write("# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of bench.py (commands in\n"
+                         "# profiles/README.md); counters are KiB per dispatch, averaged over the dispatches\n"
+                         "# of the kernel at this grid size, scaled by what they read for the copy kernels\n"
+                         "# k_copy_q of known size in the same runs\n")
+                fh.write("# fetch scale %.4f, write scale %.4f; algorithmic bytes per launch %d\n"
+                         % (f_scale, w_scale, alg))
+                fh.write("# scaled HBM bytes / algorithmic bytes = %.4f\n" % (hbm / alg))
+                fh.write("source_sha=%s\nfetch_kib_per_launch=%.1f\nwrite_kib_per_launch=%.1f\n"
+                         "fetch_scale=%.6f\nwrite_scale=%.6f\nalgorithmic_bytes_per_launch=%d\n"
+                         "hbm_bytes_per_launch=%.1f\n" % (source_hash(), fk, wk, f_scale, w_scale, alg, hbm))
+            out.append("# wrote profiles/%s: %.4e bytes per launch, %.4f x algorithmic" % (fname, hbm, hbm / alg))
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 2 and sys.argv[1] == "trace-summary":
+        print(trace_summary(sys.argv[2]))
+    elif len(sys.argv) > 3 and sys.argv[1] == "pmc-summary":
+        print(pmc_summary(sys.argv[2], sys.argv[3], write_files="--write" in sys.argv[4:]))
+    else:
+        main()

@@ -63,6 +63,16 @@ def ulp_of(x, dtype):
     return np.maximum(spacing, floor)
 
 
+def rho_spacing_bar(rho_ref, bar=1e-12):
+    """Bar for the relative L2 error of rho - 1 when rho is returned in FP64:
+    ``bar``, or one FP64 spacing of rho (2^-52 near 1) per cell in the RMS,
+    whichever is larger.  No FP64 value of rho, however accurate, carries
+    rho - 1 more finely than that spacing, and |rho - 1| is small (1e-6 ..
+    1e-3) in these flows."""
+    d = np.asarray(rho_ref, dtype=np.float64).ravel() - 1.0
+    return max(bar, 2.0 ** -52 * np.sqrt(d.size) / max(np.linalg.norm(d), 1e-300))
+
+
 def rel_l2(a, b):
     """||a - b|| / ||b||; the difference is taken in the wider of the two
     floating types (long double references keep their extra bits)."""
