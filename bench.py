@@ -578,45 +578,56 @@ PROFILED = {
 }
 
 
-def _csv_rows(directory, suffix):
-    """Rows (dicts) of every rocprofv3 CSV named *<suffix> below directory."""
-    import csv
+def _db_rows(directory, query):
+    """Rows of `query` over every rocprofv3 result database (*_results.db,
+    SQLite) below directory."""
+    import sqlite3
     rows = []
-    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
-        with open(path, newline="") as fh:
-            rows.extend(csv.DictReader(fh))
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*_results.db"), recursive=True)):
+        con = sqlite3.connect(path)
+        try:
+            rows.extend(con.execute(query).fetchall())
+        finally:
+            con.close()
     return rows
 
 
-def _col(row, *names):
-    for n in names:
-        if n in row and row[n] != "":
-            return row[n]
-    raise KeyError(names)
+# method template codes of the sweeps (collide.h) and storage types
+_METHOD_CODES = {"0": "SRT", "1": "TRT", "2": "MRT", "3": "CUMULANT", "4": "SRT_SMAG", "5": "MRT_SMAG",
+                 "6": "CUMULANT_GEN", "7": "KBC"}
+_MANGLED_TYPES = {"d": "double", "f": "float", "DF16_": "f16", "DF16b": "bf16"}
 
 
-def _kernel(row):
-    name = _col(row, "Kernel_Name", "Kernel-Name", "KernelName")
-    return name.replace("lbm::", "").replace("(anonymous namespace)::", "")
-
-
-def _grid(row):
-    try:
-        return int(_col(row, "Grid_Size", "Grid_Size_X", "Grid-Size"))
-    except KeyError:
-        return -1
+def _kernel(name, mangled=""):
+    """Kernel symbol without namespaces, argument list and template noise;
+    sweep templates as k_sweep<stencil, method, storage[, NT]> (from the
+    mangled symbol where the profiler's demangling of 16-bit types fails)."""
+    import re
+    m = re.match(r"_ZN3lbm\d+(k_sweep\w*)INS_\d(D\w+?)ELi(\d+)E(DF16_|DF16b|d|f)Li(\d)E", mangled or name)
+    if m:     # symbols the profiler could not demangle (16-bit float types)
+        return "%s<%s, %s, %s%s>" % (m.group(1), m.group(2), _METHOD_CODES.get(m.group(3), m.group(3)),
+                                    _MANGLED_TYPES[m.group(4)], ", NT" if m.group(5) == "1" else "")
+    name = re.sub(r"\(.*$", "", name.replace("lbm::", "").replace("(anonymous namespace)::", ""))
+    name = re.sub(r"^void ", "", name)
+    m = re.match(r"(k_sweep\w*)<(D\w+), (\d+), ([^,>]+), (\d)>$", name)
+    if m:
+        name = "%s<%s, %s, %s%s>" % (m.group(1), m.group(2), _METHOD_CODES.get(m.group(3), m.group(3)),
+                                    m.group(4).replace("__bf16", "bf16").replace("_Float16", "f16"),
+                                    ", NT" if m.group(5) == "1" else "")
+    name = name.replace("unsigned long", "uint64").replace("unsigned int", "uint32").replace("unsigned short",
+                                                                                              "uint16")
+    return name
 
 
 def trace_summary(directory):
     """Per (kernel, grid size) statistics of a rocprofv3 --kernel-trace run:
     calls, average / min / max duration in ns, workgroup size, VGPRs."""
     groups = {}
-    for r in _csv_rows(directory, "kernel_trace.csv"):
-        d = int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))
-        key = (_kernel(r), _grid(r))
-        g = groups.setdefault(key, {"d": [], "wg": _col(r, "Workgroup_Size", "Workgroup_Size_X"),
-                                    "vgpr": r.get("Arch_VGPR_Count", r.get("VGPR_Count", "?"))})
-        g["d"].append(d)
+    q = ("select k.name, s.kernel_name, k.grid_x, k.workgroup_x, k.vgpr_count, k.duration from kernels k "
+         "left join kernel_symbols s on k.kernel_id = s.kernel_id")
+    for name, mangled, grid, wg, vgpr, dur in _db_rows(directory, q):
+        g = groups.setdefault((_kernel(name, mangled or ""), int(grid)), {"d": [], "wg": wg, "vgpr": vgpr})
+        g["d"].append(int(dur))
     lines = [" calls       avg_ns       min_ns       max_ns        grid    wg  vgpr  kernel"]
     for (k, grid), g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"])):
         d = g["d"]
@@ -627,18 +638,17 @@ def trace_summary(directory):
 
 def _counter_means(directory, counter):
     acc = {}
-    for r in _csv_rows(directory, "counter_collection.csv"):
-        if _col(r, "Counter_Name") != counter:
-            continue
-        key = (_kernel(r), _grid(r))
-        acc.setdefault(key, []).append(float(_col(r, "Counter_Value")))
+    q = ("select c.kernel_name, s.kernel_name, c.grid_size, c.value from counters_collection c "
+         "left join kernel_symbols s on c.kernel_id = s.kernel_id where c.counter_name = '%s'" % counter)
+    for name, mangled, grid, value in _db_rows(directory, q):
+        acc.setdefault((_kernel(name, mangled or ""), int(grid)), []).append(float(value))
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
 def _copy_bytes(kernel, grid):
     """Bytes one k_copy_q<E, Q> dispatch reads (and writes) over `grid` cells."""
     import re
-    m = re.match(r"k_copy_q<uint(\d+), (\d+)>", kernel)
+    m = re.match(r"k_copy_q<uint(\d+), (\d+)>$", kernel)
     return None if not m else int(m.group(1)) // 8 * int(m.group(2)) * grid
 
 
