@@ -179,6 +179,19 @@ int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t fi
  * (out is still written). */
 int32_t lbm_conserved(lbm_ctx* ctx, double out[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals
+ * of lbm_conserved, written to totals_dev (4 doubles of device memory that
+ * the caller owns) on the context's stream, with no allocation, no host copy
+ * and no synchronisation; the caller checks them for NaN / Inf.  The partial
+ * sums go to a static device scratch of 4096 rows of 4 doubles (128 KiB,
+ * one per GPU, held until the process ends) shared by every call on that
+ * GPU: any lattice fits (its row segments are reduced in strides over at
+ * most 4096 blocks), nothing in it needs clearing, and calls on one GPU that
+ * overlap in time (on other streams or threads) race on it.
+ * LBM_EINVAL for NULL arguments. */
+int32_t lbm_conserved_noalloc(lbm_ctx* ctx, double* totals_dev);
+
 /* Copy the state out / in as unshifted FP64 PDFs, layout [q*N + i] in the
  * documented direction order.  lbm_set_pdfs rounds into the storage type and
  * resets the step counter and tape; lbm_get_pdfs synchronises. */

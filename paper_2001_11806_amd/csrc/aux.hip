@@ -5,6 +5,7 @@
 // These run once per run or once per readout, not per time step, so they
 // compute in FP64 regardless of the storage type.
 #include <algorithm>
+#include <mutex>
 
 #include "sweep.h"
 
@@ -283,6 +284,108 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
   }
   if (e != hipSuccess) return e;
   return launch_sum_partials(partials, num_blocks(g), 4, out4, 0, s);
+}
+
+// --------------------------------------------------------------- totals without allocation
+// Scratch of lbm_conserved_noalloc: one row of four FP64 partial totals per
+// block of a strided reduction, for callers that cannot allocate device
+// memory.  Every GPU holds its own copy for the life of the process.  Host
+// code never names this array in a launch or copy: it uses the device
+// address that noalloc_scratch_setup records for each device.
+__device__ __align__(256) double scratch[kNoAllocSlots * 4];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;   // the symbol address is per device: look it up there
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_dev[device] = p;
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (double*)g_scratch_dev[device];
+}
+
+// The totals of k_conserved with a bounded grid: block b sums the row
+// segments b, b + gridDim.x, ... (plain order), so gridDim.x partial rows
+// cover any lattice.
+template <class L, class T>
+__global__ __launch_bounds__(512) void k_conserved_strided(const T* __restrict__ P, const uint8_t* __restrict__ flags,
+                                                           int has_mask, int layout, double* __restrict__ partials,
+                                                           Geo g, double rho0,
+                                                           const typename Storage<T>::R* wall) {
+  double v[4] = {0, 0, 0, 0};
+  const int64_t nblk = (int64_t)g.nxb * g.ny * g.nz;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    CellIdx c;
+    const int64_t row = b / g.nxb;
+    c.x = (int)(b % g.nxb) * g.bx + (int)threadIdx.x;
+    c.y = (int)(row % g.ny);
+    c.z = (int)(row / g.ny);
+    c.cell = (int)(row * g.nx) + c.x;
+    c.valid = c.x < g.nx;
+    if (!c.valid || (has_mask && (flags[c.cell] & 1))) continue;
+    double pf[L::Q];
+    load_post<L, T>(P, flags, has_mask, layout, c, g, pf, wall, rho0);
+    double d = 0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const double f = pf[q];
+      d += f;
+      v[1] += L::c(q, 0) * f;
+      v[2] += L::c(q, 1) * f;
+      v[3] += L::c(q, 2) * f;
+    }
+    v[0] += rho0 + d;
+  }
+  block_sum<4>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partials[(size_t)blockIdx.x * 4 + k] = v[k];
+}
+
+hipError_t launch_conserved_noalloc(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                                    int layout, double* scratch_dev, int nslots, double* out4, const Geo& g,
+                                    const Params& p, hipStream_t s) {
+  if (!scratch_dev || nslots < 1 || nslots > kNoAllocSlots) return hipErrorInvalidValue;
+  auto body = [&](auto lat, auto tag) -> hipError_t {
+    using L = decltype(lat);
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_conserved_strided<L, T>), dim3((unsigned)nslots), dim3(g.bx), 0, s, (const T*)P, flags,
+                       has_mask, layout, scratch_dev, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+    return hipGetLastError();
+  };
+  auto by_dtype = [&](auto lat) -> hipError_t {
+    switch (dtype) {
+      case 0: return body(lat, double());
+      case 1: return body(lat, float());
+      case 2: return body(lat, __bf16());
+      case 3: return body(lat, _Float16());
+    }
+    return hipErrorInvalidValue;
+  };
+  hipError_t e = hipErrorInvalidValue;
+  switch (stencil) {
+    case 0: e = by_dtype(D2Q9()); break;
+    case 1: e = by_dtype(D3Q19()); break;
+    case 2: e = by_dtype(D3Q27()); break;
+  }
+  if (e != hipSuccess) return e;
+  return launch_sum_partials(scratch_dev, nslots, 4, out4, 0, s);
 }
 
 // --------------------------------------------------------------- PDF I/O

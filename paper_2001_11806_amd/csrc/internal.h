@@ -70,6 +70,18 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
 hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t* flags,
                             int has_mask, int layout, double* partials, double* out4, const Geo& g,
                             const Params& p, hipStream_t s);
+// The same totals through the library's static scratch (no allocation):
+// at most kNoAllocSlots partial rows of 4 doubles on each device.
+constexpr int kNoAllocSlots = 4096;
+constexpr int kMaxDevices = 64;
+// Record the device address of the scratch on `device` (which must be the
+// current device); idempotent.  Called by lbm_create.
+hipError_t noalloc_scratch_setup(int device);
+// That address, or NULL before setup.
+double* noalloc_scratch(int device);
+hipError_t launch_conserved_noalloc(int stencil, int dtype, const void* P, const uint8_t* flags, int has_mask,
+                                    int layout, double* scratch_dev, int nslots, double* out4, const Geo& g,
+                                    const Params& p, hipStream_t s);
 // Solid cells are read from P_solid (the buffer that keeps their values).
 hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const void* P_solid, const uint8_t* flags,
                            int has_mask, int layout, double* out, const Geo& g, const Params& p, hipStream_t s);

@@ -2,6 +2,7 @@
 // device buffers, the step loop, the checkpoint tape and the adjoint driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -60,6 +61,7 @@ struct lbm_ctx {
   Geo g{};
   Params p{};
   hipStream_t stream = nullptr;
+  int device = 0;              // device current at creation (its stream's device)
   size_t grid_bytes = 0;
   void* grid[2] = {nullptr, nullptr};
   // Buffer holding the current state: grid[0] with AA; with two arrays one
@@ -398,6 +400,14 @@ int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host, void* 
   c->p = make_params(*cfg);
   c->p.moving = moving;
   c->stream = (hipStream_t)hip_stream;
+  {
+    hipError_t e0 = hipGetDevice(&c->device);
+    if (e0 == hipSuccess) e0 = noalloc_scratch_setup(c->device);
+    if (e0 != hipSuccess) {
+      delete c;
+      return hip_fail(e0, "device scratch lookup");
+    }
+  }
   const size_t N = (size_t)c->g.N;
   c->grid_bytes = (size_t)c->Q * N * storage_bytes(cfg->dtype);
   const size_t rb = compute_bytes(cfg->dtype);
@@ -604,6 +614,17 @@ int32_t lbm_conserved(lbm_ctx* ctx, double out[4]) {
   HIP_TRY(hipStreamSynchronize(ctx->stream), "totals sync");
   for (int i = 0; i < 4; ++i)
     if (!std::isfinite(out[i])) return fail(LBM_ENONFINITE, "conservation total %d is not finite", i);
+  return LBM_OK;
+}
+
+int32_t lbm_conserved_noalloc(lbm_ctx* ctx, double* totals_dev) {
+  if (!ctx || !totals_dev) return fail(LBM_EINVAL, "NULL argument");
+  double* scr = noalloc_scratch(ctx->device);
+  if (!scr) return fail(LBM_ESTATE, "no scratch address recorded for device %d", ctx->device);
+  const int64_t nslots = std::min<int64_t>(num_blocks(ctx->g), kNoAllocSlots);
+  HIP_TRY(launch_conserved_noalloc(ctx->cfg.stencil, ctx->cfg.dtype, ctx->state, ctx->flags, ctx->has_mask,
+                                   layout_of(ctx), scr, (int)nslots, totals_dev, ctx->g, ctx->p, ctx->stream),
+          "conservation launch (no allocation)");
   return LBM_OK;
 }
 

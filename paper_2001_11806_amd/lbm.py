@@ -60,6 +60,7 @@ SIGNATURES = {
     "lbm_adjoint_seed": ([_P, _P, _P, _I32], _I32),
     "lbm_adjoint_step": ([_P, _I32], _I32),
     "lbm_adjoint_grads": ([_P, _P, _P, _I32, _DP], _I32),
+    "lbm_conserved_noalloc": ([_P, _P], _I32),
     "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _P], _I32),
     "lbm_last_error": ([], ctypes.c_char_p),
     "lbm_version": ([], _I32),
@@ -251,6 +252,15 @@ class LBM:
         out = (ctypes.c_double * 4)()
         _check(self.lib.lbm_conserved(self.h, out))
         return np.array(list(out))
+
+    def conserved_noalloc(self, out):
+        """Enqueue the totals of ``conserved`` into ``out`` (4 float64 on the
+        lattice's device) without allocating; no synchronisation."""
+        torch = self.torch
+        if out.dtype != torch.float64 or out.numel() < 4 or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous float64 tensor of >= 4 elements on " + str(self.device))
+        _check(self.lib.lbm_conserved_noalloc(self.h, _ptr(out)))
+        return out
 
     def get_pdfs(self):
         torch = self.torch
