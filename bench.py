@@ -683,10 +683,15 @@ def pmc_summary(fetch_dir, write_dir, write_files=False):
             hbm = (fk * f_scale + wk * w_scale) * 1024
             with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
                 fh.write("# HBM traffic of %s (one launch)\n" % desc)
-                fh.write("# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of bench.py (commands in\n"
-                         "# profiles/README.md); counters are KiB per dispatch, averaged over the dispatches\n"
-                         "# of the kernel at this grid size, scaled by what they read for the copy kernels\n"
-                         "# k_copy_q of known size in the same runs\n")
+                fh.write("# commands (GPU box, repository root R, TMPDIR=/tmp; one counter per run):\n"
+                         "#   rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o fetch -- python $R/bench.py "
+                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c5\n"
+                         "#   rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o write -- python $R/bench.py "
+                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c5\n"
+                         "#   python bench.py pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --write\n"
+                         "# counters are KiB per dispatch, averaged over the dispatches of the kernel at this\n"
+                         "# grid size, scaled by what they read for the copy kernels k_copy_q of known size\n"
+                         "# in the same runs\n")
                 fh.write("# fetch scale %.4f, write scale %.4f; algorithmic bytes per launch %d\n"
                          % (f_scale, w_scale, alg))
                 fh.write("# scaled HBM bytes / algorithmic bytes = %.4f\n" % (hbm / alg))
@@ -697,8 +702,36 @@ def pmc_summary(fetch_dir, write_dir, write_files=False):
     return "\n".join(out)
 
 
+def pmc_table(directory):
+    """Average of every counter of a rocprofv3 --pmc run per (kernel, grid
+    size), one row per kernel, and for the sweeps the per-cell figures of
+    the SQ counters (instructions per lane = per cell, VALU busy share)."""
+    acc = {}
+    q = ("select c.kernel_name, s.kernel_name, c.grid_size, c.counter_name, c.value from counters_collection c "
+         "left join kernel_symbols s on c.kernel_id = s.kernel_id")
+    for name, mangled, grid, cname, value in _db_rows(directory, q):
+        acc.setdefault((_kernel(name, mangled or ""), int(grid)), {}).setdefault(cname, []).append(float(value))
+    lines = []
+    for (k, grid), cs in sorted(acc.items(), key=lambda kv: -kv[0][1]):
+        if "sweep" not in k and "copy_q" not in k and "adj" not in k:
+            continue
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        extra = ""
+        if m.get("SQ_WAVES"):
+            w = m["SQ_WAVES"]
+            per = ["%s/wave %.0f" % (c[3:], m[c] / w) for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+                                                               "SQ_INSTS_VMEM_WR") if c in m]
+            if "SQ_ACTIVE_INST_VALU" in m and m.get("GRBM_GUI_ACTIVE"):
+                per.append("VALU busy %.1f %%" % (100 * m["SQ_ACTIVE_INST_VALU"] / 256 / m["GRBM_GUI_ACTIVE"]))
+            extra = "  " + ", ".join(per)
+        lines.append("%-44s grid %10d  %s%s" % (k, grid, " ".join("%s=%.4g" % kv for kv in sorted(m.items())), extra))
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 2 and sys.argv[1] == "trace-summary":
+    if len(sys.argv) > 2 and sys.argv[1] == "pmc-table":
+        print(pmc_table(sys.argv[2]))
+    elif len(sys.argv) > 2 and sys.argv[1] == "trace-summary":
         print(trace_summary(sys.argv[2]))
     elif len(sys.argv) > 3 and sys.argv[1] == "pmc-summary":
         print(pmc_summary(sys.argv[2], sys.argv[3], write_files="--write" in sys.argv[4:]))
