@@ -323,6 +323,7 @@ MATCH = {
     "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0", "sweep_d3q27_cumulant_384_f16_traffic.txt"),
     "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12", "sweep_d3q27_mrt_512_f64_traffic.txt"),
     "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0", "sweep_d3q27_mrt_512_f16_traffic.txt"),
+    "c4_d3q19_srt_adjoint_128_f32": (None, "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt"),
 }
 
 
@@ -392,7 +393,7 @@ def attach_lines(extras):
         if w not in extras:
             continue
         r = extras[w]
-        if line in extras and "achieved_GBps" in r:
+        if line and line in extras and "achieved_GBps" in r:
             r["copy_line"] = line
             r["frac_of_copy_line"] = r["achieved_GBps"] / extras[line]["GBps"]
         tr = read_traffic(prof)
@@ -573,8 +574,12 @@ PROFILED = {
         "k_sweep<D3Q27, MRT, double, NT>", 512 ** 3, 2 * 27 * 8 * 512 ** 3,
         "k_sweep<D3Q27, MRT, double> on the 512^3 periodic box (C5 FP64)"),
     "sweep_d3q27_mrt_512_f16_traffic.txt": (
-        "k_sweep<D3Q27, MRT, f16, NT>", 512 ** 3, 2 * 27 * 2 * 512 ** 3,
-        "k_sweep<D3Q27, MRT, f16> on the 512^3 periodic box (C5 FP16)"),
+        "k_sweep<D3Q27, MRT_UNIT, f16, NT>", 512 ** 3, 2 * 27 * 2 * 512 ** 3,
+        "k_sweep<D3Q27, MRT_UNIT, f16> (MRT with unit higher-order rates) on the 512^3 periodic box (C5 FP16)"),
+    "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt": (
+        "k_adj_sweep_aa<D3Q19, float, *, 0>", 128 ** 3, (19 * 4 + 2 * 19 * 4 + 1) * 128 ** 3,
+        "k_adj_sweep_aa<D3Q19, float> (even and odd) on the 128^3 channel with spheres (C4 adjoint step; "
+        "algorithmic bytes taken as (Q s + 2 Q r + 1) N over all cells)"),
 }
 
 
@@ -594,7 +599,7 @@ def _db_rows(directory, query):
 
 # method template codes of the sweeps (collide.h) and storage types
 _METHOD_CODES = {"0": "SRT", "1": "TRT", "2": "MRT", "3": "CUMULANT", "4": "SRT_SMAG", "5": "MRT_SMAG",
-                 "6": "CUMULANT_GEN", "7": "KBC"}
+                 "6": "CUMULANT_GEN", "7": "KBC", "8": "MRT_UNIT"}
 _MANGLED_TYPES = {"d": "double", "f": "float", "DF16_": "f16", "DF16b": "bf16"}
 
 

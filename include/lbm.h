@@ -107,7 +107,10 @@ typedef struct {
 } lbm_config;
 
 /* Supported combinations: SRT, TRT, MRT on all stencils (MRT rates: orders
- * 3..6 on D3Q27, orders 3 and 4 on D2Q9 and D3Q19);
+ * 3..6 on D3Q27, orders 3 and 4 on D2Q9 and D3Q19; when all of them are 1 on
+ * D2Q9 / D3Q27 with FP32 or 16-bit storage, a kernel that rebuilds the
+ * post-collision populations from their moments of order <= 2 runs instead,
+ * the same operator of Eq. (4));
  * CUMULANT on D2Q9 and D3Q27, compressible and without body force (higher-order
  * rates all 1 use a Gaussian-reconstruction kernel, other rates a general FP64
  * cumulant kernel); KBC on all stencils (shear and bulk rates fixed, one

@@ -459,7 +459,7 @@ hipError_t launch_adjoint_sweep(int stencil, int method, int dtype, int phase, c
     using MRT = std::integral_constant<int, M_MRT>;
     if (method == M_TRT) {
       if (phase == 0) go(Z(), TRT()); else go(O(), TRT());
-    } else if (method == M_MRT) {
+    } else if (method == M_MRT || method == M_MRT_UNIT) {   // the same operator
       if (phase == 0) go(Z(), MRT()); else go(O(), MRT());
     } else {
       if (phase == 0) go(Z(), SRT()); else go(O(), SRT());

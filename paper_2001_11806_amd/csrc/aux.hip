@@ -16,7 +16,7 @@ bool sweep_supported(int stencil, int method) {   // kernel method code
   if (method == M_SRT || method == M_TRT || method == M_MRT || method == M_KBC || method == M_SRT_SMAG ||
       method == M_MRT_SMAG)
     return stencil >= 0 && stencil <= 2;
-  if (method == M_CUMULANT || method == M_CUMULANT_GEN) return stencil == 0 || stencil == 2;
+  if (method == M_CUMULANT || method == M_CUMULANT_GEN || method == M_MRT_UNIT) return stencil == 0 || stencil == 2;
   return false;
 }
 

@@ -16,7 +16,8 @@ namespace lbm {
 
 // Internal method codes: the ABI's four, plus SRT and MRT with the
 // Smagorinsky model (local shear rate).
-enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5, M_CUMULANT_GEN = 6, M_KBC = 7 };
+enum { M_SRT = 0, M_TRT = 1, M_MRT = 2, M_CUMULANT = 3, M_SRT_SMAG = 4, M_MRT_SMAG = 5, M_CUMULANT_GEN = 6, M_KBC = 7,
+       M_MRT_UNIT = 8 };
 
 template <class R>
 struct CollideParams {
@@ -187,18 +188,19 @@ __device__ __forceinline__ void collide_trt(R* f, const R* F, const CollideParam
 // Groups: order 0, 1 conserved; order 2 split into shear (off-diagonal and
 // traceless diagonal, omega) and bulk (trace, omega_b); order n >= 3 hi[n-3].
 // Eq. (3) has no component of order >= 3 on these stencils.
-template <class L, class R, bool SMAG = false>
-__device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParams<R>& p) {
+// Hermite coefficients a[i][j][k] = sum_q h_i(c_x) h_j(c_y) h_k(c_z) f_q of the
+// shifted populations, h_0 = 1, h_1 = c, h_2 = 3c^2 - 1 (k = 0 only in 2-D):
+// per axis (v-, v0, v+) -> (sum, v+ - v-, 2v- - v0 + 2v+).
+template <class L, class R>
+__device__ __forceinline__ void mrt_forward(const R* f, R (&a)[3][3][(L::DIM == 3) ? 3 : 1]) {
   constexpr int D = L::DIM;
   constexpr int NK = (D == 3) ? 3 : 1;
-  R a[3][3][NK];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int k = 0; k < NK; ++k) a[i][j][k] = f[qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0)];
-  // forward 1-D transforms: (v-, v0, v+) -> (sum, v+ - v-, 2v- - v0 + 2v+)
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -228,32 +230,18 @@ __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParam
         a[i][j][NK - 1] = R(2) * (m + pp) - z;
       }
   }
-  // a[i][j][k] now holds A for Hermite orders (i, j, k) (k = 0 in 2-D)
-  const R drho = a[0][0][0];
-  const R rho = p.rho0 + drho;
-  const R rr = p.compressible ? rho : p.rho0;
-  const R inv = R(1) / rr;
-  const R ux = (a[1][0][0] + R(0.5) * F[0]) * inv;
-  const R uy = (a[0][1][0] + R(0.5) * F[1]) * inv;
-  const R uz = (D == 3) ? (a[0][0][NK > 1 ? 1 : 0] + R(0.5) * F[2]) * inv : R(0);
-  R om = p.om;
-  if constexpr (SMAG) {
-    // Pi^neq from the Hermite coefficients: off-diagonal A_ab - rr u_a u_b,
-    // diagonal (A_aa - 3 rr u_a^2) / 3 (the neq mass is zero)
-    const R xy = a[1][1][0] - rr * ux * uy;
-    const R xx = (a[2][0][0] - R(3) * rr * ux * ux) * R(1.0 / 3.0);
-    const R yy = (a[0][2][0] - R(3) * rr * uy * uy) * R(1.0 / 3.0);
-    R zz = R(0), xz = R(0), yz = R(0);
-    if constexpr (D == 3) {
-      zz = (a[0][0][NK - 1] - R(3) * rr * uz * uz) * R(1.0 / 3.0);
-      xz = a[1][0][1] - rr * ux * uz;
-      yz = a[0][1][1] - rr * uy * uz;
-    }
-    om = smagorinsky_omega(xx, yy, zz, xy, xz, yz, rho, p);
-  }
-  const R omb = p.om_b;
+}
+
+// gamma_k of orders 0..2 written over those coefficients of a (the others
+// are left alone): conserved orders 0, 1 (rate 0, Guo sigma = 3 F_a), the
+// shear group (off-diagonal and traceless diagonal, omega) and the bulk
+// trace (omega_b); rr = rho (compressible) or rho_0.
+template <class L, class R>
+__device__ __forceinline__ void mrt_gamma2(R (&a)[3][3][(L::DIM == 3) ? 3 : 1], const R* F, R rr, R ux, R uy,
+                                           R uz, R om, R omb) {
+  constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
   const R fs = R(1) - R(0.5) * om, fb = R(1) - R(0.5) * omb;
-  // gamma in place
   // order 0 and 1: conserved (rate 0); the source gives sigma = 3 F_a
   a[0][0][0] = R(0);
   a[1][0][0] = R(3) * F[0];
@@ -288,6 +276,39 @@ __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParam
     a[0][2][0] = g[1];
     if constexpr (D == 3) a[0][0][NK - 1] = g[2];
   }
+}
+
+template <class L, class R, bool SMAG = false>
+__device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
+  R a[3][3][NK];
+  mrt_forward<L>(f, a);
+  // a[i][j][k] now holds A for Hermite orders (i, j, k) (k = 0 in 2-D)
+  const R drho = a[0][0][0];
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (a[1][0][0] + R(0.5) * F[0]) * inv;
+  const R uy = (a[0][1][0] + R(0.5) * F[1]) * inv;
+  const R uz = (D == 3) ? (a[0][0][NK > 1 ? 1 : 0] + R(0.5) * F[2]) * inv : R(0);
+  R om = p.om;
+  if constexpr (SMAG) {
+    // Pi^neq from the Hermite coefficients: off-diagonal A_ab - rr u_a u_b,
+    // diagonal (A_aa - 3 rr u_a^2) / 3 (the neq mass is zero)
+    const R xy = a[1][1][0] - rr * ux * uy;
+    const R xx = (a[2][0][0] - R(3) * rr * ux * ux) * R(1.0 / 3.0);
+    const R yy = (a[0][2][0] - R(3) * rr * uy * uy) * R(1.0 / 3.0);
+    R zz = R(0), xz = R(0), yz = R(0);
+    if constexpr (D == 3) {
+      zz = (a[0][0][NK - 1] - R(3) * rr * uz * uz) * R(1.0 / 3.0);
+      xz = a[1][0][1] - rr * ux * uz;
+      yz = a[0][1][1] - rr * uy * uz;
+    }
+    om = smagorinsky_omega(xx, yy, zz, xy, xz, yz, rho, p);
+  }
+  // gamma in place
+  mrt_gamma2<L>(a, F, rr, ux, uy, uz, om, p.om_b);
   // orders >= 3: A^eq = 0, no source
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -343,6 +364,105 @@ __device__ __forceinline__ void collide_mrt(R* f, const R* F, const CollideParam
         const int q = qindex<L>(i - 1, j - 1, D == 3 ? k - 1 : 0);
         f[q] += a[i][j][k];
       }
+}
+
+// 1-D back transforms of a line with the 1-D weights (1/6, 2/3, 1/6):
+// (g0, g1, g2) -> (w-(g0 - g1 + 2g2), w0(g0 - g2), w+(g0 + g1 + 2g2)), and the
+// same for lines whose last one or two entries are zero (skipped, not added:
+// the compiler may not drop an addition of zero under IEEE rules).
+template <class R>
+__device__ __forceinline__ void back_line3(R g0, R g1, R g2, R* o) {
+  o[0] = R(1.0 / 6.0) * (g0 - g1 + R(2) * g2);
+  o[1] = R(2.0 / 3.0) * (g0 - g2);
+  o[2] = R(1.0 / 6.0) * (g0 + g1 + R(2) * g2);
+}
+template <class R>
+__device__ __forceinline__ void back_line2(R g0, R g1, R* o) {
+  o[0] = R(1.0 / 6.0) * (g0 - g1);
+  o[1] = R(2.0 / 3.0) * g0;
+  o[2] = R(1.0 / 6.0) * (g0 + g1);
+}
+template <class R>
+__device__ __forceinline__ void back_line1(R g0, R* o) {
+  o[0] = R(1.0 / 6.0) * g0;
+  o[1] = R(2.0 / 3.0) * g0;
+  o[2] = o[0];
+}
+
+// MRT with every rate of order >= 3 equal to 1 (the Kolmogorov workload):
+// Eq. (4) in the basis of collide_mrt, where relaxing those orders at rate 1
+// leaves them zero after the collision (Eq. (3) has no component there).  So
+// f* is rebuilt from its coefficients of orders <= 2 alone,
+//   f*_q = w_q sum_{|k| <= 2} H_k(c_q) c_k,  c_k = A_k / |H_k|^2 + gamma_k,
+// which needs 10 of the 27 forward coefficients (the compiler drops the
+// rest) and a back transform over lines that are mostly zero: the same
+// operator as collide_mrt with hi = 1 in about two thirds of its arithmetic.
+template <class L, class R>
+__device__ __forceinline__ void collide_mrt_unit(R* f, const R* F, const CollideParams<R>& p) {
+  constexpr int D = L::DIM;
+  constexpr int NK = (D == 3) ? 3 : 1;
+  R a[3][3][NK];
+  mrt_forward<L>(f, a);
+  const R drho = a[0][0][0];
+  const R rho = p.rho0 + drho;
+  const R rr = p.compressible ? rho : p.rho0;
+  const R inv = R(1) / rr;
+  const R ux = (a[1][0][0] + R(0.5) * F[0]) * inv;
+  const R uy = (a[0][1][0] + R(0.5) * F[1]) * inv;
+  const R uz = (D == 3) ? (a[0][0][NK > 1 ? 1 : 0] + R(0.5) * F[2]) * inv : R(0);
+  // A_k / |H_k|^2 of orders 1 and 2 before gamma overwrites them
+  const R s100 = R(3) * a[1][0][0], s010 = R(3) * a[0][1][0];
+  const R s110 = R(9) * a[1][1][0], s200 = R(0.5) * a[2][0][0], s020 = R(0.5) * a[0][2][0];
+  R s001 = R(0), s101 = R(0), s011 = R(0), s002 = R(0);
+  if constexpr (D == 3) {
+    s001 = R(3) * a[0][0][1];
+    s101 = R(9) * a[1][0][1];
+    s011 = R(9) * a[0][1][1];
+    s002 = R(0.5) * a[0][0][2];
+  }
+  mrt_gamma2<L>(a, F, rr, ux, uy, uz, p.om, p.om_b);
+  const R c000 = drho;   // gamma = 0: the mass is conserved
+  const R c100 = s100 + a[1][0][0], c010 = s010 + a[0][1][0];
+  const R c110 = s110 + a[1][1][0], c200 = s200 + a[2][0][0], c020 = s020 + a[0][2][0];
+  if constexpr (D == 3) {
+    const R c001 = s001 + a[0][0][1], c101 = s101 + a[1][0][1], c011 = s011 + a[0][1][1];
+    const R c002 = s002 + a[0][0][2];
+    // pass z: E[i][j][kk] for the (i, j) lines with a nonzero entry
+    R e00[3], e10[3], e01[3], e11[3], e20[3], e02[3];
+    back_line3(c000, c001, c002, e00);
+    back_line2(c100, c101, e10);
+    back_line2(c010, c011, e01);
+    back_line1(c110, e11);
+    back_line1(c200, e20);
+    back_line1(c020, e02);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      // pass y: G[i][jj] for this kk
+      R g0[3], g1[3], g2[3];
+      back_line3(e00[kk], e01[kk], e02[kk], g0);
+      back_line2(e10[kk], e11[kk], g1);
+      back_line1(e20[kk], g2);
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        R o[3];   // pass x
+        back_line3(g0[jj], g1[jj], g2[jj], o);
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) f[qindex<L>(ii - 1, jj - 1, kk - 1)] = o[ii];
+      }
+    }
+  } else {
+    R g0[3], g1[3], g2[3];   // pass y
+    back_line3(c000, c010, c020, g0);
+    back_line2(c100, c110, g1);
+    back_line1(c200, g2);
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      R o[3];   // pass x
+      back_line3(g0[jj], g1[jj], g2[jj], o);
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) f[qindex<L>(ii - 1, jj - 1, 0)] = o[ii];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- MRT (general stencil)
@@ -1087,6 +1207,7 @@ __device__ __forceinline__ void collide(R* f, const R* F, const CollideParams<R>
   else if constexpr (M == M_TRT) collide_trt<L>(f, F, p);
   else if constexpr (M == M_MRT && L::Q == 19) collide_mrt_gs<L>(f, F, p);
   else if constexpr (M == M_MRT) collide_mrt<L>(f, F, p);
+  else if constexpr (M == M_MRT_UNIT) collide_mrt_unit<L>(f, F, p);
   else if constexpr (M == M_MRT_SMAG && L::Q == 19) collide_mrt_gs<L, R, true>(f, F, p);
   else if constexpr (M == M_MRT_SMAG) collide_mrt<L, R, true>(f, F, p);
   else if constexpr (M == M_CUMULANT_GEN) collide_cumulant_general<L>(f, F, p);

@@ -116,11 +116,16 @@ void free_ctx(lbm_ctx* c) {
 int kernel_method(const lbm_config* cfg) {
   if (cfg->rates.cs_smag > 0) return cfg->method == LBM_SRT ? 4 : 5;
   if (cfg->method == LBM_KBC) return 7;
-  if (cfg->method == LBM_CUMULANT) {   // unit higher-order rates: the Gaussian-reconstruction kernel
-    const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;
-    for (int i = 0; i < nhi; ++i)
-      if (cfg->rates.omega_hi[i] != 1.0) return 6;
-  }
+  const int nhi = cfg->stencil == LBM_D2Q9 ? 2 : 4;   // orders 3..4 (D2Q9) or 3..6 (D3Q27) exist
+  bool unit_hi = true;
+  for (int i = 0; i < nhi; ++i) unit_hi = unit_hi && cfg->rates.omega_hi[i] == 1.0;
+  // unit higher-order rates: the Gaussian-reconstruction cumulant kernel, and
+  // on the tensor-product stencils with FP32 or 16-bit storage the MRT kernel
+  // that rebuilds f* from orders <= 2 (512^3 D3Q27 FP16: 2.779 -> 2.749 ms per
+  // step; FP64, which is far from its VALU limit, measured 1.2 % slower with
+  // it, so FP64 keeps the general kernel)
+  if (cfg->method == LBM_CUMULANT) return unit_hi ? 3 : 6;
+  if (cfg->method == LBM_MRT && cfg->stencil != LBM_D3Q19 && unit_hi && cfg->dtype != LBM_F64) return 8;
   return cfg->method;
 }
 

@@ -402,7 +402,7 @@ hipError_t run_sweep(int phase, const void* src, void* dst, const uint8_t* flags
     // 7 % at 12, FP32 cumulant, KBC, Smagorinsky)
     constexpr bool srt_trt = M == M_SRT || M == M_TRT;
     const int waves = !nt ? 0
-                      : sizeof(T) == 8 ? ((srt_trt || M == M_MRT || M == M_CUMULANT) ? 12 : 0)
+                      : sizeof(T) == 8 ? ((srt_trt || M == M_MRT || M == M_MRT_UNIT || M == M_CUMULANT) ? 12 : 0)
                       : sizeof(T) == 4 ? (srt_trt ? (L::Q == 19 ? 16 : 12) : 0)
                                        : 0;
     const unsigned lds = occupancy_lds(waves, g.bx);

@@ -17,6 +17,8 @@ hipError_t launch_sweep_d3q27(int method, int dtype, int phase, const void* src,
     case M_SRT: return sweep_for_dtype<D3Q27, M_SRT>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
     case M_TRT: return sweep_for_dtype<D3Q27, M_TRT>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
     case M_MRT: return sweep_for_dtype<D3Q27, M_MRT>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
+    case M_MRT_UNIT:
+      return sweep_for_dtype<D3Q27, M_MRT_UNIT>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
     case M_CUMULANT: return sweep_for_dtype<D3Q27, M_CUMULANT>(dtype, phase, src, dst, flags, force_y, g, p, has_mask, s);
   }
   return hipErrorInvalidValue;

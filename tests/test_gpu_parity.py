@@ -607,3 +607,82 @@ def test_streaming_segmented_rows_match_oracle(case):
     print("rel L2 u %.3e" % err)
     assert err <= (1e-12 if dtype == "f64" else 3 * BOUND_U[dtype])
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q27"])
+def test_mrt_unit_higher_rates_parity(stencil, dtype):
+    """MRT whose rates of order >= 3 are all 1 (the Kolmogorov workload) runs,
+    with FP32 and 16-bit storage, the kernel that rebuilds f* from its orders
+    <= 2 alone (FP64 keeps the general kernel, checked here too).  Against the
+    oracle's plain Eq. (4) with the same rates (shear 1/0.55, bulk 1.2),
+    walls, random solid cells and a force: 12 steps at the bars of every
+    operator; one step from the same rounded state within one storage ulp
+    plus the FP32 compute error (16-bit and FP32 storage); the AA pattern
+    equal to the two-array pattern bit for bit."""
+    need_gpu()
+    rates = dict(MRT_RATES, omega_hi=(1.0,) * 4)
+    dims, mask, rho, u, F = _setup(stencil, "MRT", dtype)
+    Ff = orun.force_field(F, dims)
+    print("case MRT unit higher rates", stencil, dtype, dims, flush=True)
+    outs = []
+    for pattern in (0, 1):
+        g = make_gpu(stencil, "MRT", dtype, dims, mask, rates, pattern=pattern)
+        g.set_force(F)
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+        g.step(STEPS)
+        outs.append((to_np(g.get_pdfs()),) + tuple(to_np(t) for t in g.macroscopic()))
+        g.close()
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0], outs[1]))
+    P_gpu, rg, ug = outs[0]
+    cfg = oracle_cfg(stencil, "MRT", "f64", rates)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), STEPS, mask, Ff)
+    ro, uo = orun.readout(cfg, P, mask, Ff)
+    err_u = rel_l2(ug, uo)
+    print("rel L2 u %.3e" % err_u)
+    assert err_u <= BOUND_U[dtype]
+    if dtype == "f64":
+        assert np.max(np.abs(P_gpu - P)) <= 1e-13
+        fluid = ro != 0
+        assert rel_l2(rg[fluid] - 1.0, ro[fluid] - 1.0) <= 1e-12
+    else:
+        g = make_gpu(stencil, "MRT", dtype, dims, mask, rates)
+        g.set_force(F)
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+        g.step(1)
+        P1 = to_np(g.get_pdfs())
+        g.close()
+        ecfg = oracle_cfg(stencil, "MRT", dtype, rates)
+        Pe = orun.run(ecfg, orun.init_equilibrium(ecfg, rho, u, mask), 1, mask, Ff)
+        w = ecfg.lat.w.reshape(-1, 1, 1, 1)
+        sg, so = P1 - w, Pe - w
+        tol = ulp_of(so, dtype) + 4e-7 * np.max(np.abs(so))
+        assert not (np.abs(sg - so) > tol).any()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q27"])
+def test_mrt_unit_higher_rates_incompressible(stencil, dtype):
+    """The unit-rate MRT kernel with the incompressible equilibrium and a
+    reference density rho_0 = 0.8 (storage shift w_q rho_0): 12 steps against
+    the oracle with the same rho_0, at the usual bars."""
+    need_gpu()
+    rates = dict(MRT_RATES, omega_hi=(1.0,) * 4)
+    dims, mask, rho, u, F = _setup(stencil, "MRT", dtype)
+    rho = 0.8 * rho
+    g = make_gpu(stencil, "MRT", dtype, dims, mask, rates, rho0=0.8, compressible=False)
+    g.set_force(F)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(STEPS)
+    P_gpu = to_np(g.get_pdfs())
+    _, ug = (to_np(t) for t in g.macroscopic())
+    g.close()
+    cfg = orun.Config(stencil, "MRT", rates, rho0=0.8, compressible=False)
+    Ff = orun.force_field(F, dims)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), STEPS, mask, Ff)
+    _, uo = orun.readout(cfg, P, mask, Ff)
+    err_u = rel_l2(ug, uo)
+    print("MRT unit rates incompressible", stencil, dtype, "rel L2 u %.3e" % err_u)
+    assert err_u <= BOUND_U[dtype]
+    if dtype == "f64":
+        assert np.max(np.abs(P_gpu - P)) <= 1e-13
