@@ -207,6 +207,11 @@ def main():
             else:
                 r["rel_l2_u_vs_f64_%d_steps" % T3] = float((uo - ref[0]).norm() / ref[0].norm())
                 r["rel_l2_rho_minus_1_vs_f64_%d_steps" % T3] = float((ro - ref[1]).norm() / (ref[1] - 1).norm())
+                # what the figures mean: FP32 against its 1e-5 bar; whether the
+                # storage resolves the density deviation at all (error < 10 %)
+                if dt == "f32":
+                    r["u_within_fp32_bar_1e-5"] = r["rel_l2_u_vs_f64_%d_steps" % T3] <= 1e-5
+                r["rho_minus_1_resolved"] = r["rel_l2_rho_minus_1_vs_f64_%d_steps" % T3] < 0.1
             extras["c3_d3q27_cumulant_384_%s" % dt] = r
             log("  %s: %.0f MLUPS, %.0f GB/s%s" % (dt, r["mlups"], r["achieved_GBps"], "" if dt == "f64" else
                 ", rel L2 vs FP64: u %.2e, rho-1 %.2e" % (r["rel_l2_u_vs_f64_%d_steps" % T3],

@@ -55,6 +55,13 @@ extern "C" {
 
 typedef struct lbm_ctx lbm_ctx;
 
+/* Status, stencil, method and storage-type codes are plain int32_t values
+ * (fixed width across compilers); the typedefs name what a value means. */
+typedef int32_t lbm_status;
+typedef int32_t lbm_stencil;
+typedef int32_t lbm_method;
+typedef int32_t lbm_dtype;
+
 /* stencils (Sec. III-A) */
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 };
 /* collision operators: Eq. (1); Sec. III-C TRT; Eq. (4); Eq. (9); Sec. III-C
@@ -63,7 +70,7 @@ enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2, LBM_CUMULANT = 3, LBM_KBC = 4 };
 /* PDF storage type (FP64 computes in FP64, the others in FP32); also used
  * to describe caller field buffers (only LBM_F64 / LBM_F32 there) */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 };
-/* status codes */
+/* status codes (lbm_status) */
 enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,        /* bad argument                                  */
@@ -88,9 +95,9 @@ typedef struct {
 } lbm_rates;
 
 typedef struct {
-  int32_t stencil;          /* LBM_D2Q9 | LBM_D3Q19 | LBM_D3Q27                    */
-  int32_t method;           /* LBM_SRT | LBM_TRT | LBM_MRT | LBM_CUMULANT | LBM_KBC */
-  int32_t dtype;            /* PDF storage type                                     */
+  lbm_stencil stencil;      /* LBM_D2Q9 | LBM_D3Q19 | LBM_D3Q27                    */
+  lbm_method method;        /* LBM_SRT | LBM_TRT | LBM_MRT | LBM_CUMULANT | LBM_KBC */
+  lbm_dtype dtype;          /* PDF storage type                                     */
   int32_t nx, ny, nz;       /* lattice size; nz == 1 for D2Q9; N < 2^31            */
   lbm_rates rates;          /* every used rate must lie in (0, 2)                   */
   double rho0;              /* reference density: storage shift and Eq. (3) rho_0  */
@@ -130,16 +137,16 @@ typedef struct {
  * hip_stream: a hipStream_t of the current device, or NULL.
  * On success *out owns all allocations; release with lbm_destroy.
  * The PDFs are initialised to rest at rho0 (shifted zero). */
-int32_t lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host,
+lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_mask_host,
                    void* hip_stream, lbm_ctx** out);
 
 /* Free everything the context owns (synchronises its stream). NULL is a no-op. */
-int32_t lbm_destroy(lbm_ctx* ctx);
+lbm_status lbm_destroy(lbm_ctx* ctx);
 
 /* Body force (Guo scheme).  F: 3 host doubles, a force constant in space; or
  * F == NULL and profile_y = ny*3 host doubles, force (Fx, Fy, Fz) of row y at
  * [3*y + a] (uniform in x and z).  Invalidates a recorded tape. */
-int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
+lbm_status lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
 
 /* Velocity of the moving-wall type `wall_type` (2..127): solid cells whose mask
  * value is wall_type act as a wall moving with u (3 host doubles).  A
@@ -148,13 +155,13 @@ int32_t lbm_set_force(lbm_ctx* ctx, const double* F, const double* profile_y);
  * bounce-back, Sec. III-C "Boundary Conditions").  Mask value 1 is the resting
  * wall; all types start at rest.  With pattern 1 call it before
  * lbm_init_equilibrium / lbm_set_pdfs.  Invalidates a recorded tape. */
-int32_t lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u);
+lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t wall_type, const double* u);
 
 /* P = f^eq(rho, u) (Eq. 3) at fluid cells; resets the step counter and tape.
  * rho_dev: N values or NULL (rho0 everywhere); u_dev: 3*N values or NULL
  * (at rest); both of type field_dtype (LBM_F64 or LBM_F32). */
-int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
-                             int32_t field_dtype);
+lbm_status lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_dev,
+                             lbm_dtype field_dtype);
 
 /* Advance n >= 0 time steps.  One step is the pull streaming of Sec. IV-B
  * (Fig. "stream-pull-collide": each cell gathers population q from its
@@ -168,19 +175,19 @@ int32_t lbm_init_equilibrium(lbm_ctx* ctx, const void* rho_dev, const void* u_de
  * writes it there directly), and so are the states of the last k-step
  * segment below max_tape_steps, which an adjoint started in or at the end of
  * that segment then need not recompute. */
-int32_t lbm_step(lbm_ctx* ctx, int32_t n);
+lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Readout of the stored (post-collision) state by Eq. (2): rho = sum f,
  * u = (sum c f - F/2) / rho_0 (rho_0 = rho when compressible; the F/2 term
  * makes u the Guo velocity of the collision that produced the state).
  * rho_dev: N or NULL, u_dev: 3*N or NULL, of type field_dtype. */
-int32_t lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, int32_t field_dtype);
+lbm_status lbm_get_macroscopic(lbm_ctx* ctx, void* rho_dev, void* u_dev, lbm_dtype field_dtype);
 
 /* FP64 totals over fluid cells of the moments of Eq. (2): out[0] = sum of
  * rho = sum_q f_q, out[1..3] = sum of the momentum sum_q c_q f_q (without
  * the F/2 shift).  Synchronises.  LBM_ENONFINITE if any total is NaN/Inf
  * (out is still written). */
-int32_t lbm_conserved(lbm_ctx* ctx, double out[4]);
+lbm_status lbm_conserved(lbm_ctx* ctx, double out[4]);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the totals
@@ -193,16 +200,16 @@ int32_t lbm_conserved(lbm_ctx* ctx, double out[4]);
  * most 4096 blocks), nothing in it needs clearing, and calls on one GPU that
  * overlap in time (on other streams or threads) race on it.
  * LBM_EINVAL for NULL arguments. */
-int32_t lbm_conserved_noalloc(lbm_ctx* ctx, double* totals_dev);
+lbm_status lbm_conserved_noalloc(lbm_ctx* ctx, double* totals_dev);
 
 /* Copy the state out / in as unshifted FP64 PDFs, layout [q*N + i] in the
  * documented direction order.  lbm_set_pdfs rounds into the storage type and
  * resets the step counter and tape; lbm_get_pdfs synchronises. */
-int32_t lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev);
-int32_t lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
+lbm_status lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev);
+lbm_status lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
 
 /* Number of steps taken since the last init / set_pdfs. */
-int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t);
+lbm_status lbm_get_time(lbm_ctx* ctx, int64_t* t);
 
 /* ---- discrete adjoint (SRT, TRT and MRT, compressible) ------------------
  * Forward map: P^0 = f^eq(rho_init, u_init) from lbm_init_equilibrium,
@@ -216,16 +223,16 @@ int32_t lbm_get_time(lbm_ctx* ctx, int64_t* t);
  * Seed lambda^T from dL/drho and dL/du at the current step T (fields of type
  * field_dtype, dL_drho_dev may be NULL).  Needs checkpoint_every > 0 and
  * T <= max_tape_steps, else LBM_ESTATE. */
-int32_t lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_du_dev,
-                         int32_t field_dtype);
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* dL_drho_dev, const void* dL_du_dev,
+                         lbm_dtype field_dtype);
 /* Run n adjoint steps backwards (n <= steps remaining, else LBM_ESTATE);
  * recomputes the forward states of each k-step segment from the tape. */
-int32_t lbm_adjoint_step(lbm_ctx* ctx, int32_t n);
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n);
 /* Once the adjoint has reached t = 0: dL/du_init (3*N), dL/drho_init (N,
  * or NULL) of type field_dtype, and dL/dF (3 host doubles, accumulated in
  * FP64, or NULL).  Synchronises when dL_dF != NULL. */
-int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
-                          int32_t field_dtype, double* dL_dF);
+lbm_status lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
+                          lbm_dtype field_dtype, double* dL_dF);
 
 /* Bandwidth reference: copy Q planes of n elements of elem_bytes (2, 4 or 8)
  * from src to dst with the sweep's thread layout (one thread per cell, Q
@@ -234,7 +241,7 @@ int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
  * at most k wavefronts per CU (the launch shape of a sweep that runs so;
  * values the LDS split cannot express fall back to full occupancy), < 0 or
  * > 32 is LBM_EINVAL.  hip_stream as in lbm_create. */
-int32_t lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q,
+lbm_status lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q,
                    int32_t elem_bytes, int32_t waves_per_cu, void* hip_stream);
 
 /* Thread-local description of the last error. */
