@@ -304,30 +304,31 @@ def main():
 
 # Copy references (the paper's multi-stream copy benchmark, Sec. V-A, Tab. III):
 # Q read and Q write SoA streams of the workload's size and element type, in
-# the launch shape (waves per CU, 0 = full occupancy) of the sweep compared
-# with them.  Key -> (Q, lattice edge, storage, element bytes, waves per CU).
+# the launch shape of the sweep compared with them (waves per CU, 0 = full
+# occupancy; threads per block = the sweep's row segment) and with its store
+# type (non-temporal above 512 MiB).  Key -> (Q, lattice edge, storage,
+# element bytes, waves per CU, threads per block).
 COPIES = {
-    "copy_q19_f64_256_w12": (19, 256, "f64", 8, 12),   # C2 FP64 two-array sweep
-    "copy_q19_f64_256_w0": (19, 256, "f64", 8, 0),     # C2 FP64 AA sweeps
-    "copy_q19_f32_256_w16": (19, 256, "f32", 4, 16),   # C2 FP32 two-array sweep
-    "copy_q19_f16_256_w0": (19, 256, "f16", 2, 0),
-    "copy_q27_f64_384_w12": (27, 384, "f64", 8, 12),   # C3 FP64 (error reference)
-    "copy_q27_f32_384_w0": (27, 384, "f32", 4, 0),     # C3 FP32 cumulant
-    "copy_q27_f16_384_w0": (27, 384, "f16", 2, 0),     # C3 BF16 / FP16 cumulant
-    "copy_q27_f64_512_w12": (27, 512, "f64", 8, 12),   # C5 FP64 MRT
-    "copy_q27_f16_512_w0": (27, 512, "f16", 2, 0),     # C5 FP16 MRT
+    "copy_q19_f64_256_w12_b256": (19, 256, "f64", 8, 12, 256),   # C2 FP64 two-array sweep
+    "copy_q19_f64_256_w0_b256": (19, 256, "f64", 8, 0, 256),     # C2 FP64 AA sweeps
+    "copy_q19_f32_256_w16_b256": (19, 256, "f32", 4, 16, 256),   # C2 FP32 two-array sweep
+    "copy_q27_f64_384_w12_b384": (27, 384, "f64", 8, 12, 384),   # C3 FP64 (error reference)
+    "copy_q27_f32_384_w0_b384": (27, 384, "f32", 4, 0, 384),     # C3 FP32 cumulant
+    "copy_q27_f16_384_w0_b128": (27, 384, "f16", 2, 0, 128),     # C3 BF16 / FP16 cumulant (128-cell segments)
+    "copy_q27_f64_512_w12_b512": (27, 512, "f64", 8, 12, 512),   # C5 FP64 MRT
+    "copy_q27_f16_512_w0_b512": (27, 512, "f16", 2, 0, 512),     # C5 FP16 MRT
 }
 # workload -> (matching copy line, committed counter summary of its sweep kernel)
 MATCH = {
-    "c2_d3q19_trt_256_f64": ("copy_q19_f64_256_w12", "sweep_d3q19_trt_256_f64_traffic.txt"),
-    "c2_d3q19_trt_256_f32": ("copy_q19_f32_256_w16", "sweep_d3q19_trt_256_f32_traffic.txt"),
-    "c2_d3q19_trt_256_f64_aa": ("copy_q19_f64_256_w0", "sweep_aa_d3q19_trt_256_f64_traffic.txt"),
-    "c3_d3q27_cumulant_384_f64": ("copy_q27_f64_384_w12", "sweep_d3q27_cumulant_384_f64_traffic.txt"),
-    "c3_d3q27_cumulant_384_f32": ("copy_q27_f32_384_w0", "sweep_d3q27_cumulant_384_f32_traffic.txt"),
-    "c3_d3q27_cumulant_384_bf16": ("copy_q27_f16_384_w0", "sweep_d3q27_cumulant_384_bf16_traffic.txt"),
-    "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0", "sweep_d3q27_cumulant_384_f16_traffic.txt"),
-    "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12", "sweep_d3q27_mrt_512_f64_traffic.txt"),
-    "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0", "sweep_d3q27_mrt_512_f16_traffic.txt"),
+    "c2_d3q19_trt_256_f64": ("copy_q19_f64_256_w12_b256", "sweep_d3q19_trt_256_f64_traffic.txt"),
+    "c2_d3q19_trt_256_f32": ("copy_q19_f32_256_w16_b256", "sweep_d3q19_trt_256_f32_traffic.txt"),
+    "c2_d3q19_trt_256_f64_aa": ("copy_q19_f64_256_w0_b256", "sweep_aa_d3q19_trt_256_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f64": ("copy_q27_f64_384_w12_b384", "sweep_d3q27_cumulant_384_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f32": ("copy_q27_f32_384_w0_b384", "sweep_d3q27_cumulant_384_f32_traffic.txt"),
+    "c3_d3q27_cumulant_384_bf16": ("copy_q27_f16_384_w0_b128", "sweep_d3q27_cumulant_384_bf16_traffic.txt"),
+    "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0_b128", "sweep_d3q27_cumulant_384_f16_traffic.txt"),
+    "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12_b512", "sweep_d3q27_mrt_512_f64_traffic.txt"),
+    "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0_b512", "sweep_d3q27_mrt_512_f16_traffic.txt"),
     "c4_d3q19_srt_adjoint_128_f32": (None, "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt"),
 }
 
@@ -340,15 +341,15 @@ def bench_copies(torch, copy_q, Timer, dev):
     import ctypes
     out = {}
     st = torch.cuda.current_stream(dev)
-    for key, (q, n, dt, eb, waves) in COPIES.items():
+    for key, (q, n, dt, eb, waves, block) in COPIES.items():
         N = n ** 3
         src = torch.empty(q * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
         for _ in range(3):
-            copy_q(src, dst, N, q, eb, st, waves)
+            copy_q(src, dst, N, q, eb, st, waves, block)
         with Timer(torch, st) as t:
             for _ in range(20):
-                copy_q(src, dst, N, q, eb, st, waves)
+                copy_q(src, dst, N, q, eb, st, waves, block)
         gbps = 2 * q * N * eb * 20 / (t.ms / 1e3) / 1e9
         out[key] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
         log("%s: %.0f GB/s" % (key, gbps))
@@ -658,7 +659,7 @@ def _counter_means(directory, counter):
 def _copy_bytes(kernel, grid):
     """Bytes one k_copy_q<E, Q> dispatch reads (and writes) over `grid` cells."""
     import re
-    m = re.match(r"k_copy_q<uint(\d+), (\d+)>$", kernel)
+    m = re.match(r"k_copy_q<uint(\d+), (\d+)(, \d)?>$", kernel)
     return None if not m else int(m.group(1)) // 8 * int(m.group(2)) * grid
 
 

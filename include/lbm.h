@@ -236,13 +236,16 @@ lbm_status lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
 
 /* Bandwidth reference: copy Q planes of n elements of elem_bytes (2, 4 or 8)
  * from src to dst with the sweep's thread layout (one thread per cell, Q
- * loads and Q stores).  The analogue of the paper's multi-stream copy
- * benchmark (Sec. V-A, Tab. III).  waves_per_cu: 0 = full occupancy, k > 0 =
- * at most k wavefronts per CU (the launch shape of a sweep that runs so;
- * values the LDS split cannot express fall back to full occupancy), < 0 or
- * > 32 is LBM_EINVAL.  hip_stream as in lbm_create. */
+ * loads and Q stores, non-temporal stores once the arrays exceed 512 MiB as
+ * in the sweep).  The analogue of the paper's multi-stream copy benchmark
+ * (Sec. V-A, Tab. III).  waves_per_cu: 0 = full occupancy, k > 0 = at most k
+ * wavefronts per CU (the launch shape of a sweep that runs so; values the
+ * LDS split cannot express fall back to full occupancy), < 0 or > 32 is
+ * LBM_EINVAL.  block_threads: threads per block, 0 = 256, else a multiple of
+ * 64 in 64..512 (a sweep's row-segment length), otherwise LBM_EINVAL.
+ * hip_stream as in lbm_create. */
 lbm_status lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q,
-                   int32_t elem_bytes, int32_t waves_per_cu, void* hip_stream);
+                   int32_t elem_bytes, int32_t waves_per_cu, int32_t block_threads, void* hip_stream);
 
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);

@@ -475,40 +475,61 @@ hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t*
 
 // --------------------------------------------------------------- copy-Q
 // Bandwidth reference: same thread layout and access pattern as the sweep
-// (all Q loads, then all Q stores), without the gather offsets or arithmetic.
-template <class E, int Q>
-__global__ __launch_bounds__(256) void k_copy_q(const E* __restrict__ src, E* __restrict__ dst, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// (all Q loads, then all Q stores; blocks of the sweep's row length), without
+// the gather offsets or arithmetic.  Arrays larger than the caches store
+// non-temporally, as the sweep does.
+template <class E, int Q, int NT>
+__global__ __launch_bounds__(512) void k_copy_q(const E* __restrict__ src, E* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   E v[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) v[q] = src[q * n + i];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) dst[q * n + i] = v[q];
+  for (int q = 0; q < Q; ++q) {
+    if (NT)
+      __builtin_nontemporal_store(v[q], dst + q * n + i);
+    else
+      dst[q * n + i] = v[q];
+  }
 }
 
-template <class E>
-__global__ __launch_bounds__(256) void k_copy_generic(const E* __restrict__ src, E* __restrict__ dst, int64_t n,
+template <class E, int NT>
+__global__ __launch_bounds__(512) void k_copy_generic(const E* __restrict__ src, E* __restrict__ dst, int64_t n,
                                                       int Q) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int q = 0; q < Q; ++q) dst[q * n + i] = src[q * n + i];
+  for (int q = 0; q < Q; ++q) {
+    if (NT)
+      __builtin_nontemporal_store(src[q * n + i], dst + q * n + i);
+    else
+      dst[q * n + i] = src[q * n + i];
+  }
 }
 
-// The copy reference runs with the occupancy the caller names (the launch
-// shape of the sweep it is compared with): at most waves_per_cu wavefronts
-// per CU, 0 = full occupancy.
-template <class E>
-hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, int waves_per_cu, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const unsigned lds = occupancy_lds(waves_per_cu, 256);
+// The copy reference runs with the occupancy and block size the caller names
+// (the launch shape of the sweep it is compared with): at most waves_per_cu
+// wavefronts per CU (0 = full occupancy), block_threads per block.
+template <class E, int NT>
+hipError_t copy_q_nt(const void* src, void* dst, int64_t n, int q, int waves_per_cu, int block_threads,
+                     hipStream_t s) {
+  const dim3 grid((unsigned)((n + block_threads - 1) / block_threads)), block(block_threads);
+  const unsigned lds = occupancy_lds(waves_per_cu, block_threads);
   switch (q) {
-    case 9: hipLaunchKernelGGL((k_copy_q<E, 9>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
-    case 19: hipLaunchKernelGGL((k_copy_q<E, 19>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
-    case 27: hipLaunchKernelGGL((k_copy_q<E, 27>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
-    default: hipLaunchKernelGGL((k_copy_generic<E>), grid, block, lds, s, (const E*)src, (E*)dst, n, q);
+    case 9: hipLaunchKernelGGL((k_copy_q<E, 9, NT>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    case 19: hipLaunchKernelGGL((k_copy_q<E, 19, NT>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    case 27: hipLaunchKernelGGL((k_copy_q<E, 27, NT>), grid, block, lds, s, (const E*)src, (E*)dst, n); break;
+    default: hipLaunchKernelGGL((k_copy_generic<E, NT>), grid, block, lds, s, (const E*)src, (E*)dst, n, q);
   }
   return hipGetLastError();
+}
+
+template <class E>
+hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, int waves_per_cu, int block_threads,
+                        hipStream_t s) {
+  if ((size_t)n * (size_t)q * sizeof(E) > kStreamGridBytes)
+    return copy_q_nt<E, 1>(src, dst, n, q, waves_per_cu, block_threads, s);
+  return copy_q_nt<E, 0>(src, dst, n, q, waves_per_cu, block_threads, s);
 }
 
 unsigned occupancy_lds(int waves_per_cu, int block_threads) {
@@ -528,11 +549,11 @@ unsigned occupancy_lds(int waves_per_cu, int block_threads) {
 }
 
 hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, int waves_per_cu,
-                         hipStream_t s) {
+                         int block_threads, hipStream_t s) {
   switch (elem_bytes) {
-    case 2: return copy_q_typed<uint16_t>(src, dst, n, q, waves_per_cu, s);
-    case 4: return copy_q_typed<uint32_t>(src, dst, n, q, waves_per_cu, s);
-    case 8: return copy_q_typed<uint64_t>(src, dst, n, q, waves_per_cu, s);
+    case 2: return copy_q_typed<uint16_t>(src, dst, n, q, waves_per_cu, block_threads, s);
+    case 4: return copy_q_typed<uint32_t>(src, dst, n, q, waves_per_cu, block_threads, s);
+    case 8: return copy_q_typed<uint64_t>(src, dst, n, q, waves_per_cu, block_threads, s);
   }
   return hipErrorInvalidValue;
 }

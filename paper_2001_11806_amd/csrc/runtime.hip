@@ -760,12 +760,17 @@ int32_t lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev, in
 }
 
 int32_t lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q, int32_t elem_bytes,
-                   int32_t waves_per_cu, void* hip_stream) {
+                   int32_t waves_per_cu, int32_t block_threads, void* hip_stream) {
   if (!src_dev || !dst_dev) return fail(LBM_EINVAL, "NULL buffer");
   if (n < 1 || q < 1) return fail(LBM_EINVAL, "n and q must be >= 1");
   if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return fail(LBM_EINVAL, "elem_bytes must be 2, 4 or 8");
   if (waves_per_cu < 0 || waves_per_cu > 32) return fail(LBM_EINVAL, "waves_per_cu must be in 0..32");
-  HIP_TRY(launch_copy_q(src_dev, dst_dev, n, q, elem_bytes, waves_per_cu, (hipStream_t)hip_stream), "copy_q launch");
+  if (block_threads == 0) block_threads = 256;
+  if (block_threads < 64 || block_threads > 512 || block_threads % 64 != 0)
+    return fail(LBM_EINVAL, "block_threads must be 0 or a multiple of 64 in 64..512");
+  if ((n + block_threads - 1) / block_threads > 0x7fffffff) return fail(LBM_EINVAL, "n too large for one launch");
+  HIP_TRY(launch_copy_q(src_dev, dst_dev, n, q, elem_bytes, waves_per_cu, block_threads, (hipStream_t)hip_stream),
+          "copy_q launch");
   return LBM_OK;
 }
 

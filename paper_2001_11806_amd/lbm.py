@@ -61,7 +61,7 @@ SIGNATURES = {
     "lbm_adjoint_step": ([_P, _I32], _I32),
     "lbm_adjoint_grads": ([_P, _P, _P, _I32, _DP], _I32),
     "lbm_conserved_noalloc": ([_P, _P], _I32),
-    "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _P], _I32),
+    "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _I32, _P], _I32),
     "lbm_last_error": ([], ctypes.c_char_p),
     "lbm_version": ([], _I32),
 }
@@ -297,9 +297,9 @@ class LBM:
         return du, dr, np.array(list(dF))
 
 
-def copy_q(src, dst, n, q, elem_bytes, stream, waves_per_cu=0):
+def copy_q(src, dst, n, q, elem_bytes, stream, waves_per_cu=0, block_threads=0):
     """Q-stream copy bandwidth reference (see include/lbm.h); waves_per_cu
-    0 = full occupancy."""
+    0 = full occupancy, block_threads 0 = 256."""
     lib = load_library()
     _check(lib.lbm_copy_q(_ptr(src), _ptr(dst), int(n), int(q), int(elem_bytes), int(waves_per_cu),
-                          ctypes.c_void_p(stream.cuda_stream)))
+                          int(block_threads), ctypes.c_void_p(stream.cuda_stream)))

@@ -100,11 +100,13 @@ def test_validation_before_device_work(lib, kw, code, msg):
 def test_null_arguments(lib):
     assert lib.lbm_step(None, 1) == B.EINVAL
     assert lib.lbm_destroy(None) == B.OK
-    assert lib.lbm_copy_q(None, None, 10, 19, 8, 0, None) == B.EINVAL
+    assert lib.lbm_copy_q(None, None, 10, 19, 8, 0, 0, None) == B.EINVAL
     fake = ctypes.c_void_p(4096)        # never dereferenced: validation comes first
-    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 33, None) == B.EINVAL
-    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, -1, None) == B.EINVAL
-    assert lib.lbm_copy_q(fake, fake, 10, 19, 3, 0, None) == B.EINVAL
+    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 33, 0, None) == B.EINVAL
+    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, -1, 0, None) == B.EINVAL
+    assert lib.lbm_copy_q(fake, fake, 10, 19, 3, 0, 0, None) == B.EINVAL
+    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 0, 96, None) == B.EINVAL
+    assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 0, 1024, None) == B.EINVAL
     assert lib.lbm_create(None, None, None, None) == B.EINVAL
     assert lib.lbm_version() >= 10000
 
