@@ -155,6 +155,24 @@ def seed(cfg, P, solid, F, dL_du, dL_drho=None):
     return lam, dF
 
 
+def transpose_gather(lat, h, solid):
+    """Transpose of the pull gather with halfway bounce-back (``stream_pull``):
+    the value h_q(x) that a fluid cell x pulled along link q goes back to the
+    slot it was read from, (x - c_q, q) for an ordinary link or (x, opp q)
+    when x - c_q is solid.  Each fluid slot is read by exactly one link, so
+    this is a permutation of fluid slots; solid-cell slots receive nothing."""
+    s = solid.astype(bool)
+    fl = ~s
+    out = np.zeros_like(h)
+    for q in range(lat.Q):
+        src_solid = _shift(s, lat.c[q])
+        link = fl & ~src_solid
+        bb = fl & src_solid
+        out[q] += _shift(np.where(link, h[q], 0.0), -lat.c[q])
+        out[lat.opp[q]] += np.where(bb, h[q], 0.0)
+    return out
+
+
 def adjoint_step(cfg, P_t, lam_next, solid, F, wall_velocity=None):
     """lambda^t from lambda^{t+1}, plus this step's dL/dF contribution.  The
     moving-wall term of the gather is a constant: it shifts the state at which
@@ -169,14 +187,8 @@ def adjoint_step(cfg, P_t, lam_next, solid, F, wall_velocity=None):
     h = np.einsum("qpn,qn->pn", J, lam2).reshape(g.shape)
     dF_cell = np.einsum("qbn,qn->bn", B, lam2).reshape((3,) + shp)
     dF = np.array([dF_cell[b][fl].sum() for b in range(3)])
-    lam = np.zeros_like(lam_next)
-    lam[:, s] = lam_next[:, s]             # identity map at solid cells
-    for q in range(lat.Q):
-        src_solid = _shift(s, lat.c[q])
-        link = fl & ~src_solid
-        bb = fl & src_solid
-        lam[q] += _shift(np.where(link, h[q], 0.0), -lat.c[q])
-        lam[lat.opp[q]] += np.where(bb, h[q], 0.0)
+    lam = transpose_gather(lat, h, solid)
+    lam[:, s] = lam_next[:, s]             # identity map at solid cells (no fluid link writes there)
     return lam, dF
 
 

@@ -48,6 +48,16 @@ REAL = {"f64": np.float64, "ld": np.longdouble}
 OrcConfig = CONFIG["f64"]
 
 
+def build_sanitized():
+    """The FP64 oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (g++), for the host-sanitizer test; loaded in place of the plain build
+    when LBM_ORACLE_LIB names it (with gcc's ASan runtime preloaded)."""
+    out = os.path.join(HERE, "liblbm_oracle_san.so")
+    subprocess.check_call(["g++", *FLAGS, "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", SRC, "-o", out])
+    return out
+
+
 def build(verbose=True):
     """Compile the oracle library (FP64, and the long double variant) with
     g++ and OpenMP; always recompiles."""
@@ -68,7 +78,7 @@ def load(precision="f64"):
     building it first if it is not there."""
     if precision in _libs:
         return _libs[precision]
-    path = {"f64": LIB, "ld": LIB_LD}[precision]
+    path = {"f64": os.environ.get("LBM_ORACLE_LIB", LIB), "ld": LIB_LD}[precision]
     if not os.path.exists(path):
         build(verbose=False)
     lib = ctypes.CDLL(path)

@@ -189,3 +189,29 @@ def test_complex_step_identity_catches_a_wrong_jacobian(monkeypatch):
     cs = adjoint.tangent_complex_step(cfg, rho, u0, mask, F, T, du, dF)
     rev = float((gu * du).sum() + gF @ dF)
     assert abs(rev / cs - 1) > 1e-6
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+def test_transpose_gather_is_a_permutation_of_fluid_slots(stencil):
+    """Write-count check of the adjoint's reverse streaming: pushing a 1
+    back along every link of every fluid cell lands exactly one 1 in every
+    slot of every fluid cell (each slot is read by exactly one link: its own
+    pull, or the bounce-back of its cell) and nothing in solid cells; and
+    <gather(P), H> = <P, transpose(H)> on fluid cells for random P, H."""
+    from oracle.lattice import velocity_set
+    from oracle.stream import stream_pull
+    lat = velocity_set(stencil)
+    dims = (9, 8, 1) if stencil == "D2Q9" else (7, 8, 5)
+    rng = np.random.default_rng(21)
+    solid = (rng.random(dims[::-1]) < 0.2).astype(np.uint8)
+    solid[..., 0, :] = 1
+    fl = solid == 0
+    ones = np.where(fl[None], 1.0, 0.0) * np.ones((lat.Q,) + dims[::-1])
+    got = adjoint.transpose_gather(lat, ones, solid)
+    assert np.array_equal(got[:, fl], np.ones((lat.Q, int(fl.sum()))))
+    assert not got[:, ~fl].any()
+    P = rng.standard_normal((lat.Q,) + dims[::-1])
+    H = rng.standard_normal(P.shape) * fl[None]
+    lhs = float((stream_pull(lat, P, solid) * H).sum())
+    rhs = float((P * adjoint.transpose_gather(lat, H, solid) * fl[None]).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
