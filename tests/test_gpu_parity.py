@@ -720,3 +720,28 @@ def test_checkpoint_resume_equals_uninterrupted_run(dtype, pattern):
     b.close()
     for x, y in zip(got, want):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("dtype,steps", [("f32", 300), ("f64", 800)])
+def test_unstable_run_is_reported_nonfinite(dtype, steps, pattern):
+    """Failure detection without faults: SRT at omega = 1.999 (tau -> 1/2)
+    with |u| up to 0.4 and rho 1 +- 0.3 on a 32^2 periodic D2Q9 box grows
+    without bound (the oracle passes 1e258 after 400 steps); once the
+    populations overflow, lbm_conserved reports LBM_ENONFINITE instead of
+    returning totals."""
+    need_gpu()
+    from paper_2001_11806_amd.lbm import LBM, LBMError
+    rng = np.random.default_rng(5)
+    n = 32
+    u = rng.uniform(-0.4, 0.4, (3, 1, n, n))
+    u[2] = 0
+    rho = 1 + rng.uniform(-0.3, 0.3, (1, n, n))
+    g = LBM("D2Q9", "SRT", dtype, (n, n, 1), 1.999, pattern=pattern)
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.conserved()                       # finite at the start
+    g.step(steps)
+    with pytest.raises(LBMError, match="not finite") as e:
+        g.conserved()
+    assert e.value.status == -6
+    g.close()
