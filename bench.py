@@ -497,11 +497,12 @@ def bench_adjoint(torch, LBM, inputs, Timer, pattern=0):
 def cpu_baseline(inputs):
     """The C++ FP64 oracle as it stands (plain loops, OpenMP over rows) on all
     the host threads it sees, on bounded samples: the headline workload on
-    its full 256^3 channel for as many steps as fit in about 15 s (at least
-    one), then a 384 x 384 x 16 slab of the cumulant workload and a
-    512 x 512 x 8 slab of the Kolmogorov MRT workload, two steps each (their
-    full lattices would need 24 GB and 58 GB of host memory for two FP64
-    arrays).  Returns the headline figure and the per-workload samples."""
+    its full 256^3 channel for as many steps as fit in about 12 s (at least
+    one, at most 100), then a 384 x 384 x 16 slab of the cumulant workload
+    and a 512 x 512 x 16 slab of the Kolmogorov MRT workload, six steps each
+    (their full lattices would need 24 GB and 58 GB of host memory for two
+    FP64 arrays).  Every sample is timed after one untimed step that touches
+    both arrays.  Returns the headline figure and the per-workload samples."""
     from oracle import cpu as ocpu, run as orun
     threads = ocpu.num_threads()
     host = {"threads": threads, "os_cpu_count": os.cpu_count(),
@@ -518,8 +519,12 @@ def cpu_baseline(inputs):
     F = np.array([1e-6, 0.0, 0.0])
     P = ocpu.init_equilibrium(cfg, None, u, mask)
     del u
+    # each call allocates its output array, so a call's time is a fixed
+    # first-touch cost plus the steps: estimate the per-step time from the
+    # difference of a one-step and a three-step call
     P, t1 = timed(cfg, P, 1, mask, F)
-    steps = int(max(1, min(20, 15.0 // max(t1, 1e-3))))
+    P, t3 = timed(cfg, P, 3, mask, F)
+    steps = int(max(1, min(100, 12.0 // max((t3 - t1) / 2, 1e-3))))
     P, dt = timed(cfg, P, steps, mask, F)
     del P
     head = n ** 3 * steps / dt / 1e6
@@ -528,16 +533,18 @@ def cpu_baseline(inputs):
     cells = np.arange(384 * 384 * 16)
     u3 = inputs.solenoidal_velocity_at(384, inputs.solenoidal_modes(seed=3), cells).reshape(3, 16, 384, 384)
     c3 = orun.Config("D3Q27", "CUMULANT", dict(omega=1 / 0.55, omega_bulk=1.0, omega_hi=(1.0,) * 4))
-    P, dt = timed(c3, ocpu.init_equilibrium(c3, None, u3), 2)
-    samples["c3_d3q27_cumulant_f64"] = {"mlups": u3[0].size * 2 / dt / 1e6, "steps": 2, "seconds": dt,
+    P, _ = timed(c3, ocpu.init_equilibrium(c3, None, u3), 1)
+    P, dt = timed(c3, P, 6)
+    samples["c3_d3q27_cumulant_f64"] = {"mlups": u3[0].size * 6 / dt / 1e6, "steps": 6, "seconds": dt,
                                         "lattice": [384, 384, 16]}
     del P, u3
-    u5 = inputs.uniform_noise_velocity((512, 512, 8), 1e-3, 5, None)
+    u5 = inputs.uniform_noise_velocity((512, 512, 16), 1e-3, 5, None)
     c5 = orun.Config("D3Q27", "MRT", dict(omega=1 / 0.55, omega_bulk=1.2, omega_hi=(1.0,) * 4))
     prof = inputs.kolmogorov_force_profile(512, 1e-6)
-    P, dt = timed(c5, ocpu.init_equilibrium(c5, None, u5), 2, None, prof)
-    samples["c5_d3q27_mrt_f64"] = {"mlups": u5[0].size * 2 / dt / 1e6, "steps": 2, "seconds": dt,
-                                   "lattice": [512, 512, 8]}
+    P, _ = timed(c5, ocpu.init_equilibrium(c5, None, u5), 1, None, prof)
+    P, dt = timed(c5, P, 6, None, prof)
+    samples["c5_d3q27_mrt_f64"] = {"mlups": u5[0].size * 6 / dt / 1e6, "steps": 6, "seconds": dt,
+                                   "lattice": [512, 512, 16]}
     del P, u5
     log("CPU oracle samples: C3 %.2f MLUPS, C5 %.2f MLUPS" % (samples["c3_d3q27_cumulant_f64"]["mlups"],
                                                               samples["c5_d3q27_mrt_f64"]["mlups"]))
@@ -632,7 +639,12 @@ def _kernel(name, mangled=""):
 
 def trace_summary(directory):
     """Per (kernel, grid size) statistics of a rocprofv3 --kernel-trace run:
-    calls, average / min / max duration in ns, workgroup size, VGPRs."""
+    calls, average / min / max duration in ns, workgroup size, VGPRs
+    allocated per lane.  rocprofv3 derives its VGPR count from the code
+    object's granule field in units of 4 registers, while gfx950 allocates
+    VGPRs in granules of 8, so the allocation is twice the figure it records
+    (k_sweep<D3Q19, TRT, double>: 74 VGPRs in the code object, 80
+    allocated, 40 recorded)."""
     groups = {}
     q = ("select k.name, s.kernel_name, k.grid_x, k.workgroup_x, k.vgpr_count, k.duration from kernels k "
          "left join kernel_symbols s on k.kernel_id = s.kernel_id")
@@ -642,8 +654,9 @@ def trace_summary(directory):
     lines = [" calls       avg_ns       min_ns       max_ns        grid    wg  vgpr  kernel"]
     for (k, grid), g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"])):
         d = g["d"]
+        vg = 2 * int(g["vgpr"]) if g["vgpr"] is not None else "-"
         lines.append("%6d %12.0f %12d %12d %11d %5s %5s  %s" % (len(d), sum(d) / len(d), min(d), max(d), grid,
-                                                             g["wg"], g["vgpr"], k))
+                                                             g["wg"], vg, k))
     return "\n".join(lines)
 
 
@@ -696,9 +709,9 @@ def pmc_summary(fetch_dir, write_dir, write_files=False):
                 fh.write("# HBM traffic of %s (one launch)\n" % desc)
                 fh.write("# commands (GPU box, repository root R, TMPDIR=/tmp; one counter per run):\n"
                          "#   rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o fetch -- python $R/bench.py "
-                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c5\n"
+                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c4,c5\n"
                          "#   rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o write -- python $R/bench.py "
-                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c5\n"
+                         "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c4,c5\n"
                          "#   python bench.py pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --write\n"
                          "# counters are KiB per dispatch, averaged over the dispatches of the kernel at this\n"
                          "# grid size, scaled by what they read for the copy kernels k_copy_q of known size\n"
