@@ -139,7 +139,7 @@ def main():
 
     import torch
     from paper_2001_11806_amd import inputs
-    from paper_2001_11806_amd.lbm import LBM, copy_q
+    from paper_2001_11806_amd.lbm import LBM, copy_q, stream_q
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -186,7 +186,7 @@ def main():
     torch.cuda.empty_cache()
 
     if want("copy"):
-        extras.update(bench_copies(torch, copy_q, Timer, dev))
+        extras.update(bench_copies(torch, copy_q, stream_q, Timer, dev))
 
     if want("c3"):
         # the full 500-step run in every storage type; FP64 on the same GPU
@@ -266,8 +266,8 @@ def main():
     extras["c2_d3q19_trt_256_f64"] = {"fluid_mlups": head["fluid_mlups"], "achieved_GBps": head["achieved_GBps"],
                                       "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"]}
     attach_lines(extras)
-    traffic = read_traffic(MATCH["c2_d3q19_trt_256_f64"][1])
-    line = MATCH["c2_d3q19_trt_256_f64"][0]
+    line, sline, prof = MATCH["c2_d3q19_trt_256_f64"]
+    traffic = read_traffic(prof)
     result = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -294,6 +294,10 @@ def main():
                      "copy_line_GBps": extras.get(line, {}).get("GBps"),
                      "frac_of_copy_line": (head["achieved_GBps"] / extras[line]["GBps"]
                                            if line in extras else None),
+                     # the same sweep's access pattern without its arithmetic
+                     "stream_line_GBps": extras.get(sline, {}).get("GBps"),
+                     "frac_of_stream_line": (head["achieved_GBps"] / extras[sline]["GBps"]
+                                             if sline in extras else None),
                      "memcpy_d2d_GBps": extras.get("memcpy_d2d_4GiB", {}).get("GBps")},
         "cpu_baseline": cpu,
         "extras": extras,
@@ -302,54 +306,92 @@ def main():
     print(json.dumps(result))
 
 
-# Copy references (the paper's multi-stream copy benchmark, Sec. V-A, Tab. III):
-# Q read and Q write SoA streams of the workload's size and element type, in
-# the launch shape of the sweep compared with them (waves per CU, 0 = full
-# occupancy; threads per block = the sweep's row segment) and with its store
-# type (non-temporal above 512 MiB).  Key -> (Q, lattice edge, storage,
-# element bytes, waves per CU, threads per block).
-COPIES = {
-    "copy_q19_f64_256_w12_b256": (19, 256, "f64", 8, 12, 256),   # C2 FP64 two-array sweep
-    "copy_q19_f64_256_w0_b256": (19, 256, "f64", 8, 0, 256),     # C2 FP64 AA sweeps
-    "copy_q19_f32_256_w16_b256": (19, 256, "f32", 4, 16, 256),   # C2 FP32 two-array sweep
-    "copy_q27_f64_384_w12_b384": (27, 384, "f64", 8, 12, 384),   # C3 FP64 (error reference)
-    "copy_q27_f32_384_w0_b384": (27, 384, "f32", 4, 0, 384),     # C3 FP32 cumulant
-    "copy_q27_f16_384_w0_b128": (27, 384, "f16", 2, 0, 128),     # C3 BF16 / FP16 cumulant (128-cell segments)
-    "copy_q27_f64_512_w12_b512": (27, 512, "f64", 8, 12, 512),   # C5 FP64 MRT
-    "copy_q27_f16_512_w0_b512": (27, 512, "f16", 2, 0, 512),     # C5 FP16 MRT
+# Bandwidth references, each in the launch shape of the sweep compared with
+# it (resident wavefronts per CU: the LDS-capped count the sweep runs with,
+# or the count its registers allow when that is lower; threads per block =
+# the sweep's row segment) and with its store type (non-temporal above
+# 512 MiB), over arrays of the workload's size and element type:
+#   copy_*   Q read and Q write SoA streams, element i to element i (the
+#            paper's multi-stream copy benchmark, Sec. V-A, Tab. III);
+#   stream_* the sweep's pull access pattern without its arithmetic:
+#            periodic pull streaming dst[q][x] = src[q][x - c_q].
+# Key -> (kind, stencil, lattice edge, storage, element bytes, waves per CU
+# (0 = full occupancy), threads per block).
+LINES = {
+    # C2 FP64 two-array sweep (12 waves per CU)
+    "copy_q19_f64_256_w12_b256": ("copy", "D3Q19", 256, "f64", 8, 12, 256),
+    "stream_d3q19_f64_256_w12_b256": ("stream", "D3Q19", 256, "f64", 8, 12, 256),
+    # C2 FP64 AA sweeps (full occupancy = 16 waves per CU at their 120-128 VGPRs)
+    "copy_q19_f64_256_w16_b256": ("copy", "D3Q19", 256, "f64", 8, 16, 256),
+    "stream_d3q19_f64_256_w16_b256": ("stream", "D3Q19", 256, "f64", 8, 16, 256),
+    # C2 FP32 two-array sweep (16 waves per CU)
+    "copy_q19_f32_256_w16_b256": ("copy", "D3Q19", 256, "f32", 4, 16, 256),
+    "stream_d3q19_f32_256_w16_b256": ("stream", "D3Q19", 256, "f32", 4, 16, 256),
+    # C3 FP64 cumulant, the error reference (12 waves per CU)
+    "copy_q27_f64_384_w12_b384": ("copy", "D3Q27", 384, "f64", 8, 12, 384),
+    "stream_d3q27_f64_384_w12_b384": ("stream", "D3Q27", 384, "f64", 8, 12, 384),
+    # C3 FP32 cumulant (full occupancy: five 384-cell blocks per CU)
+    "copy_q27_f32_384_w0_b384": ("copy", "D3Q27", 384, "f32", 4, 0, 384),
+    "stream_d3q27_f32_384_w0_b384": ("stream", "D3Q27", 384, "f32", 4, 0, 384),
+    # C3 BF16 / FP16 cumulant (128-cell segments, full occupancy)
+    "copy_q27_f16_384_w0_b128": ("copy", "D3Q27", 384, "f16", 2, 0, 128),
+    "stream_d3q27_f16_384_w0_b128": ("stream", "D3Q27", 384, "f16", 2, 0, 128),
+    # C5 FP64 MRT (256-cell segments, 12 waves per CU: the register limit)
+    "copy_q27_f64_512_w12_b256": ("copy", "D3Q27", 512, "f64", 8, 12, 256),
+    "stream_d3q27_f64_512_w12_b256": ("stream", "D3Q27", 512, "f64", 8, 12, 256),
+    # C5 FP16 MRT (512-cell rows, full occupancy)
+    "copy_q27_f16_512_w0_b512": ("copy", "D3Q27", 512, "f16", 2, 0, 512),
+    "stream_d3q27_f16_512_w0_b512": ("stream", "D3Q27", 512, "f16", 2, 0, 512),
 }
-# workload -> (matching copy line, committed counter summary of its sweep kernel)
+# workload -> (matching copy line, matching pull-stream line, committed
+# counter summary of its sweep kernel)
 MATCH = {
-    "c2_d3q19_trt_256_f64": ("copy_q19_f64_256_w12_b256", "sweep_d3q19_trt_256_f64_traffic.txt"),
-    "c2_d3q19_trt_256_f32": ("copy_q19_f32_256_w16_b256", "sweep_d3q19_trt_256_f32_traffic.txt"),
-    "c2_d3q19_trt_256_f64_aa": ("copy_q19_f64_256_w0_b256", "sweep_aa_d3q19_trt_256_f64_traffic.txt"),
-    "c3_d3q27_cumulant_384_f64": ("copy_q27_f64_384_w12_b384", "sweep_d3q27_cumulant_384_f64_traffic.txt"),
-    "c3_d3q27_cumulant_384_f32": ("copy_q27_f32_384_w0_b384", "sweep_d3q27_cumulant_384_f32_traffic.txt"),
-    "c3_d3q27_cumulant_384_bf16": ("copy_q27_f16_384_w0_b128", "sweep_d3q27_cumulant_384_bf16_traffic.txt"),
-    "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0_b128", "sweep_d3q27_cumulant_384_f16_traffic.txt"),
-    "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12_b512", "sweep_d3q27_mrt_512_f64_traffic.txt"),
-    "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0_b512", "sweep_d3q27_mrt_512_f16_traffic.txt"),
-    "c4_d3q19_srt_adjoint_128_f32": (None, "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt"),
+    "c2_d3q19_trt_256_f64": ("copy_q19_f64_256_w12_b256", "stream_d3q19_f64_256_w12_b256",
+                             "sweep_d3q19_trt_256_f64_traffic.txt"),
+    "c2_d3q19_trt_256_f32": ("copy_q19_f32_256_w16_b256", "stream_d3q19_f32_256_w16_b256",
+                             "sweep_d3q19_trt_256_f32_traffic.txt"),
+    "c2_d3q19_trt_256_f64_aa": ("copy_q19_f64_256_w16_b256", "stream_d3q19_f64_256_w16_b256",
+                                "sweep_aa_d3q19_trt_256_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f64": ("copy_q27_f64_384_w12_b384", "stream_d3q27_f64_384_w12_b384",
+                                  "sweep_d3q27_cumulant_384_f64_traffic.txt"),
+    "c3_d3q27_cumulant_384_f32": ("copy_q27_f32_384_w0_b384", "stream_d3q27_f32_384_w0_b384",
+                                  "sweep_d3q27_cumulant_384_f32_traffic.txt"),
+    "c3_d3q27_cumulant_384_bf16": ("copy_q27_f16_384_w0_b128", "stream_d3q27_f16_384_w0_b128",
+                                   "sweep_d3q27_cumulant_384_bf16_traffic.txt"),
+    "c3_d3q27_cumulant_384_f16": ("copy_q27_f16_384_w0_b128", "stream_d3q27_f16_384_w0_b128",
+                                  "sweep_d3q27_cumulant_384_f16_traffic.txt"),
+    "c5_d3q27_mrt_512_f64": ("copy_q27_f64_512_w12_b256", "stream_d3q27_f64_512_w12_b256",
+                             "sweep_d3q27_mrt_512_f64_traffic.txt"),
+    "c5_d3q27_mrt_512_f16": ("copy_q27_f16_512_w0_b512", "stream_d3q27_f16_512_w0_b512",
+                             "sweep_d3q27_mrt_512_f16_traffic.txt"),
+    "c4_d3q19_srt_adjoint_128_f32": (None, None, "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt"),
 }
 
 
-def bench_copies(torch, copy_q, Timer, dev):
-    """Copy lines of every configured workload, plus two copies that owe
-    nothing to this library: hipMemcpyAsync device to device (called
-    directly in the HIP runtime torch loaded) and torch's Tensor.copy_, each
-    on a 4 GiB buffer."""
+def bench_copies(torch, copy_q, stream_q, Timer, dev):
+    """Copy and pull-stream lines of every configured workload, plus two
+    copies that owe nothing to this library: hipMemcpyAsync device to device
+    (called directly in the HIP runtime torch loaded) and torch's
+    Tensor.copy_, each on a 4 GiB buffer."""
     import ctypes
     out = {}
     st = torch.cuda.current_stream(dev)
-    for key, (q, n, dt, eb, waves, block) in COPIES.items():
+    for key, (kind, stencil, n, dt, eb, waves, block) in LINES.items():
+        q = 19 if stencil == "D3Q19" else 27
         N = n ** 3
         src = torch.empty(q * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
+
+        def run():
+            if kind == "copy":
+                copy_q(src, dst, N, q, eb, st, waves, block)
+            else:
+                stream_q(src, dst, (n, n, n), stencil, eb, st, waves, block)
         for _ in range(3):
-            copy_q(src, dst, N, q, eb, st, waves, block)
+            run()
         with Timer(torch, st) as t:
             for _ in range(20):
-                copy_q(src, dst, N, q, eb, st, waves, block)
+                run()
         gbps = 2 * q * N * eb * 20 / (t.ms / 1e3) / 1e9
         out[key] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
         log("%s: %.0f GB/s" % (key, gbps))
@@ -392,16 +434,19 @@ def bench_copies(torch, copy_q, Timer, dev):
 
 
 def attach_lines(extras):
-    """Per workload: the matching copy line, the fraction of it reached, and
-    the counter-measured HBM bytes per launch while the committed summary
-    matches the kernel sources."""
-    for w, (line, prof) in MATCH.items():
+    """Per workload: the matching copy and pull-stream lines, the fraction of
+    each reached, and the counter-measured HBM bytes per launch while the
+    committed summary matches the kernel sources."""
+    for w, (line, sline, prof) in MATCH.items():
         if w not in extras:
             continue
         r = extras[w]
         if line and line in extras and "achieved_GBps" in r:
             r["copy_line"] = line
             r["frac_of_copy_line"] = r["achieved_GBps"] / extras[line]["GBps"]
+        if sline and sline in extras and "achieved_GBps" in r:
+            r["stream_line"] = sline
+            r["frac_of_stream_line"] = r["achieved_GBps"] / extras[sline]["GBps"]
         tr = read_traffic(prof)
         r["traffic"] = tr
         if tr is not None and "algorithmic_bytes_per_launch" in r:
@@ -737,7 +782,7 @@ def pmc_table(directory):
         acc.setdefault((_kernel(name, mangled or ""), int(grid)), {}).setdefault(cname, []).append(float(value))
     lines = []
     for (k, grid), cs in sorted(acc.items(), key=lambda kv: -kv[0][1]):
-        if "sweep" not in k and "copy_q" not in k and "adj" not in k:
+        if "sweep" not in k and "copy_q" not in k and "stream_q" not in k and "adj" not in k:
             continue
         m = {c: sum(v) / len(v) for c, v in cs.items()}
         extra = ""

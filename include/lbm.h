@@ -247,6 +247,23 @@ lbm_status lbm_adjoint_grads(lbm_ctx* ctx, void* dL_du0_dev, void* dL_drho0_dev,
 lbm_status lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q,
                    int32_t elem_bytes, int32_t waves_per_cu, int32_t block_threads, void* hip_stream);
 
+/* Bandwidth reference for the pull access pattern: periodic pull streaming
+ * of the stencil's Q planes with no collision and no walls,
+ * dst[q][x] = src[q][x - c_q] (the streaming half of Eq. (1), Sec. IV-B), in
+ * the sweep's launch shape: one block per x-row segment of block_threads
+ * cells (0 = the sweep's own segmentation, rows of up to 512 cells), the
+ * sweep's addressing, and non-temporal stores once the Q planes exceed
+ * 512 MiB.  src_dev and dst_dev hold Q planes of nx*ny*nz elements of
+ * elem_bytes (2, 4 or 8; layout [q][z][y][x]) and must not overlap.  Its
+ * rate is what the sweep's loads and stores reach without arithmetic.
+ * waves_per_cu as in lbm_copy_q.  Errors (LBM_EINVAL, before any device
+ * work): NULL buffer, unknown stencil, dims < 1 or nx*ny*nz >= 2^31, nz != 1
+ * with D2Q9, elem_bytes, waves_per_cu or block_threads out of range.
+ * hip_stream as in lbm_create. */
+lbm_status lbm_stream_q(const void* src_dev, void* dst_dev, int32_t nx, int32_t ny, int32_t nz,
+                     lbm_stencil stencil, int32_t elem_bytes, int32_t waves_per_cu,
+                     int32_t block_threads, void* hip_stream);
+
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);
 

@@ -532,6 +532,66 @@ hipError_t copy_q_typed(const void* src, void* dst, int64_t n, int q, int waves_
   return copy_q_nt<E, 0>(src, dst, n, q, waves_per_cu, block_threads, s);
 }
 
+// Pull-streaming reference: the sweep's access pattern without its
+// arithmetic.  Every cell pulls plane q from its periodic upstream neighbour
+// x - c_q and stores it in its own slot, dst[q][x] = src[q][x - c_q], with
+// the sweep's addressing (scalar row bases, one block per row segment) and
+// store type, so its rate is what the sweep's loads and stores reach with no
+// collision in between.
+template <class L, class E, int NT>
+__global__ __launch_bounds__(512) void k_stream_q(const E* __restrict__ src, E* __restrict__ dst, Geo g) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  LBM_NEIGHBOURS(c, g)
+  const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(E), (uint32_t)c.x * (uint32_t)sizeof(E),
+                          (uint32_t)xm * (uint32_t)sizeof(E)};  // source x for c_x = -1, 0, +1
+  E v[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    v[q] = *at_bytes(row_base<L>(src, q, c.y, c.z, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]);
+  E* row = dst + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    E* d = at_bytes(row + (size_t)q * (size_t)g.N, ox[1]);
+    if (NT)
+      __builtin_nontemporal_store(v[q], d);
+    else
+      *d = v[q];
+  }
+}
+
+template <class L, class E>
+hipError_t stream_q_typed(const void* src, void* dst, const Geo& g, int waves_per_cu, hipStream_t s) {
+  const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
+  const unsigned lds = occupancy_lds(waves_per_cu, g.bx);
+  if ((size_t)g.N * L::Q * sizeof(E) > kStreamGridBytes)
+    hipLaunchKernelGGL((k_stream_q<L, E, 1>), grid, block, lds, s, (const E*)src, (E*)dst, g);
+  else
+    hipLaunchKernelGGL((k_stream_q<L, E, 0>), grid, block, lds, s, (const E*)src, (E*)dst, g);
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t stream_q_stencil(const void* src, void* dst, const Geo& g, int elem_bytes, int waves_per_cu,
+                            hipStream_t s) {
+  switch (elem_bytes) {
+    case 2: return stream_q_typed<L, uint16_t>(src, dst, g, waves_per_cu, s);
+    case 4: return stream_q_typed<L, uint32_t>(src, dst, g, waves_per_cu, s);
+    case 8: return stream_q_typed<L, uint64_t>(src, dst, g, waves_per_cu, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stream_q(const void* src, void* dst, int stencil, const Geo& g, int elem_bytes,
+                           int waves_per_cu, hipStream_t s) {
+  switch (stencil) {
+    case 0: return stream_q_stencil<D2Q9>(src, dst, g, elem_bytes, waves_per_cu, s);
+    case 1: return stream_q_stencil<D3Q19>(src, dst, g, elem_bytes, waves_per_cu, s);
+    case 2: return stream_q_stencil<D3Q27>(src, dst, g, elem_bytes, waves_per_cu, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 unsigned occupancy_lds(int waves_per_cu, int block_threads) {
   static int lds_per_cu[64];   // LDS bytes per CU of each device, queried once
   int dev = 0;

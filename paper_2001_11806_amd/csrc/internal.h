@@ -91,6 +91,9 @@ hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t*
                            int layout, void* out, const Geo& g, const Params& p, hipStream_t s);
 hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_bytes, int waves_per_cu,
                          int block_threads, hipStream_t s);
+// pull-streaming reference over the row-segment launch shape of g
+hipError_t launch_stream_q(const void* src, void* dst, int stencil, const Geo& g, int elem_bytes,
+                           int waves_per_cu, hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc,
                                int accumulate, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);

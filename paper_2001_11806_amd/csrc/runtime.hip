@@ -195,6 +195,13 @@ Geo make_geo(const lbm_config& c) {
   if (half && c.method == LBM_CUMULANT && c.stencil == LBM_D3Q27 && g.nxb == 1 && c.nx % 128 == 0 &&
       32 % (c.nx / 64) != 0)
     g.nxb = c.nx / 128;
+  // The FP64 MRT kernels on D3Q27 (with or without the Smagorinsky model)
+  // need 135-150 VGPRs per lane, so a SIMD holds 3 of their wavefronts (12
+  // per CU): a 512-cell row block (8 wavefronts) leaves a third of them
+  // empty, 256-cell segments fill all 12 (512^3: 11.24 -> 11.01 ms per step,
+  // alternating processes)
+  if (c.dtype == LBM_F64 && c.stencil == LBM_D3Q27 && c.method == LBM_MRT && g.nxb == 1 && c.nx > 256)
+    g.nxb = (c.nx + 255) / 256;
   const int per = (c.nx + g.nxb - 1) / g.nxb;
   g.bx = ((per + 63) / 64) * 64;
   g.N = (int64_t)c.nx * c.ny * c.nz;
@@ -771,6 +778,31 @@ int32_t lbm_copy_q(const void* src_dev, void* dst_dev, int64_t n, int32_t q, int
   if ((n + block_threads - 1) / block_threads > 0x7fffffff) return fail(LBM_EINVAL, "n too large for one launch");
   HIP_TRY(launch_copy_q(src_dev, dst_dev, n, q, elem_bytes, waves_per_cu, block_threads, (hipStream_t)hip_stream),
           "copy_q launch");
+  return LBM_OK;
+}
+
+int32_t lbm_stream_q(const void* src_dev, void* dst_dev, int32_t nx, int32_t ny, int32_t nz, lbm_stencil stencil,
+                     int32_t elem_bytes, int32_t waves_per_cu, int32_t block_threads, void* hip_stream) {
+  if (!src_dev || !dst_dev) return fail(LBM_EINVAL, "NULL buffer");
+  if (stencil < 0 || stencil > 2) return fail(LBM_EINVAL, "unknown stencil %d", stencil);
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_EINVAL, "lattice dims must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "lattice has %lld cells; the limit is 2^31 - 1", (long long)N);
+  if (stencil == LBM_D2Q9 && nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return fail(LBM_EINVAL, "elem_bytes must be 2, 4 or 8");
+  if (waves_per_cu < 0 || waves_per_cu > 32) return fail(LBM_EINVAL, "waves_per_cu must be in 0..32");
+  if (block_threads < 0 || block_threads > 512 || block_threads % 64 != 0)
+    return fail(LBM_EINVAL, "block_threads must be 0 or a multiple of 64 in 64..512");
+  Geo g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  // 0: the sweep's default segmentation (rows of up to 512 cells in equal segments)
+  g.nxb = block_threads ? (nx + block_threads - 1) / block_threads : (nx + 511) / 512;
+  g.bx = block_threads ? block_threads : (((nx + g.nxb - 1) / g.nxb + 63) / 64) * 64;
+  g.N = N;
+  HIP_TRY(launch_stream_q(src_dev, dst_dev, stencil, g, elem_bytes, waves_per_cu, (hipStream_t)hip_stream),
+          "stream_q launch");
   return LBM_OK;
 }
 

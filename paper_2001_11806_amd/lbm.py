@@ -62,6 +62,7 @@ SIGNATURES = {
     "lbm_adjoint_grads": ([_P, _P, _P, _I32, _DP], _I32),
     "lbm_conserved_noalloc": ([_P, _P], _I32),
     "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _I32, _P], _I32),
+    "lbm_stream_q": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P], _I32),
     "lbm_last_error": ([], ctypes.c_char_p),
     "lbm_version": ([], _I32),
 }
@@ -303,3 +304,13 @@ def copy_q(src, dst, n, q, elem_bytes, stream, waves_per_cu=0, block_threads=0):
     lib = load_library()
     _check(lib.lbm_copy_q(_ptr(src), _ptr(dst), int(n), int(q), int(elem_bytes), int(waves_per_cu),
                           int(block_threads), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def stream_q(src, dst, dims, stencil, elem_bytes, stream, waves_per_cu=0, block_threads=0):
+    """Pull-streaming bandwidth reference (see include/lbm.h): dst[q][x] =
+    src[q][x - c_q], periodic, in the sweep's launch shape; dims = (nx, ny,
+    nz), block_threads 0 = the sweep's own row segmentation."""
+    lib = load_library()
+    nx, ny, nz = (int(d) for d in dims)
+    _check(lib.lbm_stream_q(_ptr(src), _ptr(dst), nx, ny, nz, STENCILS[stencil], int(elem_bytes),
+                            int(waves_per_cu), int(block_threads), ctypes.c_void_p(stream.cuda_stream)))

@@ -107,6 +107,15 @@ def test_null_arguments(lib):
     assert lib.lbm_copy_q(fake, fake, 10, 19, 3, 0, 0, None) == B.EINVAL
     assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 0, 96, None) == B.EINVAL
     assert lib.lbm_copy_q(fake, fake, 10, 19, 8, 0, 1024, None) == B.EINVAL
+    assert lib.lbm_stream_q(None, fake, 8, 8, 8, 1, 8, 0, 0, None) == B.EINVAL
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 3, 8, 0, 0, None) == B.EINVAL      # stencil
+    assert lib.lbm_stream_q(fake, fake, 0, 8, 8, 1, 8, 0, 0, None) == B.EINVAL      # dims
+    assert lib.lbm_stream_q(fake, fake, 2048, 2048, 512, 1, 8, 0, 0, None) == B.EINVAL   # 2^31 cells
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 2, 0, 8, 0, 0, None) == B.EINVAL      # D2Q9, nz != 1
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 1, 0, 0, None) == B.EINVAL      # elem_bytes
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 33, 0, None) == B.EINVAL     # waves
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 0, 100, None) == B.EINVAL    # block
+    assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 0, 576, None) == B.EINVAL
     assert lib.lbm_create(None, None, None, None) == B.EINVAL
     assert lib.lbm_version() >= 10000
 

@@ -315,7 +315,9 @@ def test_aa_pattern_equals_two_arrays(stencil, method, dtype):
     ctxs = []
     for pattern in (0, 1):
         g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern)
-        if F is not None:
+        if F is not None and np.ndim(F) == 2:
+            g.set_force(profile=F)
+        elif F is not None:
             g.set_force(F)
         g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
         ctxs.append(g)
@@ -558,16 +560,18 @@ def test_kbc_near_equilibrium_parity(stencil, dtype):
         assert np.max(np.abs(P_gpu - P)) <= 1e-13
 
 
-@pytest.mark.parametrize("case", ["d2q9_f64_srt_1100", "d3q27_f16_cumulant_384"])
+@pytest.mark.parametrize("case", ["d2q9_f64_srt_1100", "d3q27_f16_cumulant_384", "d3q27_f64_mrt_512"])
 def test_streaming_segmented_rows_match_oracle(case):
     """Lattices above 512 MiB (non-temporal stores, plain block order) whose
     rows are split into x-segments, with both patterns.
     D2Q9 SRT FP64 on 1100 x 6856 (three segments per row, 543 MB per grid,
-    walls and a force) and the D3Q27 unit-rate cumulant in FP16 on
-    384 x 160 x 168 (128-cell segments as at 384^3, 557 MB per grid): the
-    C++ oracle's bars after 5 steps (FP64: every population within 1e-13;
-    FP16: relative L2 of u within three times the 12-step FP16 bound), and
-    the AA pattern equal to the two-array pattern bit for bit."""
+    walls and a force), the D3Q27 unit-rate cumulant in FP16 on
+    384 x 160 x 168 (128-cell segments as at 384^3, 557 MB per grid) and the
+    D3Q27 MRT in FP64 on 512 x 64 x 80 (two 256-cell segments per row as at
+    512^3, 566 MB per grid, the Kolmogorov force profile): the C++ oracle's
+    bars after 5 steps (FP64: every population within 1e-13; FP16: relative
+    L2 of u within three times the 12-step FP16 bound), and the AA pattern
+    equal to the two-array pattern bit for bit."""
     need_gpu()
     from oracle import cpu as ocpu
     if case.startswith("d2q9"):
@@ -575,16 +579,24 @@ def test_streaming_segmented_rows_match_oracle(case):
         mask, rho, u = seeded_fields(stencil, dims, 9)
         F = np.array([2e-4, -1e-4, 0.0])
         rates = _rates(method)
-    else:
+    elif case.startswith("d3q27_f16"):
         stencil, method, dtype, dims = "D3Q27", "CUMULANT", "f16", (384, 160, 168)
         mask, F = None, None
         rng = np.random.default_rng(10)
         rho = 1.0 + 0.01 * rng.uniform(-1, 1, dims[::-1])
         u = inputs.uniform_noise_velocity(dims, 2e-2, 10, None)
         rates = dict(_rates("CUMULANT"), omega_hi=(1.0,) * 4, omega_bulk=1.0)
+    else:
+        stencil, method, dtype, dims = "D3Q27", "MRT", "f64", (512, 64, 80)
+        mask = None
+        rng = np.random.default_rng(12)
+        rho = 1.0 + 0.01 * rng.uniform(-1, 1, dims[::-1])
+        u = inputs.uniform_noise_velocity(dims, 2e-2, 12, None)
+        F = inputs.kolmogorov_force_profile(dims[1], 1e-5)
+        rates = _rates("MRT")
     Q = {"D2Q9": 9, "D3Q27": 27}[stencil]
     assert Q * dims[0] * dims[1] * dims[2] * (8 if dtype == "f64" else 2) > 512 * 2 ** 20
-    assert dims[0] > 512 or dtype == "f16"
+    assert dims[0] > 512 or dtype == "f16" or method == "MRT"
     T = 5
     cfg = orun.Config(stencil, method, rates, storage=dtype)
     P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, rho, u, mask), T, mask, F)
@@ -593,7 +605,9 @@ def test_streaming_segmented_rows_match_oracle(case):
     for pattern in (0, 1):
         print("case segmented rows", case, "pattern", pattern, flush=True)
         g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern)
-        if F is not None:
+        if F is not None and np.ndim(F) == 2:
+            g.set_force(profile=F)
+        elif F is not None:
             g.set_force(F)
         g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
         g.step(T)
