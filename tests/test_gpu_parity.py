@@ -798,3 +798,44 @@ def test_streaming_random_solids_match_oracle(dtype):
     print("rel L2 u %.3e" % err)
     assert err <= (1e-12 if dtype == "f64" else BOUND_U["f32"])
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+def test_solid_face_rows_match_oracle(stencil, pattern):
+    """Masks whose y rows at the domain faces are solid in every cell (three
+    at the bottom, two moving-wall rows at the top, so fluid cells sit two
+    rows deep in wall) plus one solid row inside, both patterns: FP64 TRT
+    with a force against the oracle after 12 steps, every population within
+    1e-13 (solid cells keep their initial values)."""
+    need_gpu()
+    dims = (141, 24, 1) if stencil == "D2Q9" else (141, 24, 5)
+    nx, ny, nz = dims
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[:, :3, :] = 1
+    mask[:, 22:, :] = 2
+    mask[:, 11, :] = 1
+    rng = np.random.default_rng(31)
+    rho = 1.0 + 0.01 * rng.uniform(-1, 1, (nz, ny, nx))
+    u = inputs.uniform_noise_velocity(dims, 2e-2, 131, mask)
+    if stencil == "D2Q9":
+        u[2] = 0
+    F = np.array([1e-4, 0.0, 2e-5 if stencil != "D2Q9" else 0.0])
+    table = WALL_TABLE.copy()
+    if stencil == "D2Q9":
+        table[:, 2] = 0
+    rates = _rates("TRT")
+    print("case solid face rows", stencil, "pattern", pattern, flush=True)
+    g = make_gpu(stencil, "TRT", "f64", dims, mask, rates, pattern=pattern)
+    g.set_force(F)
+    g.set_wall_velocity(2, table[2])
+    g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+    g.step(STEPS)
+    Pg = to_np(g.get_pdfs())
+    g.close()
+    cfg = oracle_cfg(stencil, "TRT", "f64", rates)
+    Ff = orun.force_field(F, dims)
+    P = orun.run(cfg, orun.init_equilibrium(cfg, rho, u, mask), STEPS, mask, Ff, table)
+    dP = float(np.max(np.abs(Pg - P)))
+    print("max |dP| %.2e" % dP)
+    assert dP <= 1e-13
