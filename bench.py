@@ -790,8 +790,11 @@ def pmc_table(directory):
             w = m["SQ_WAVES"]
             per = ["%s/wave %.0f" % (c[3:], m[c] / w) for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
                                                                "SQ_INSTS_VMEM_WR") if c in m]
-            if "SQ_ACTIVE_INST_VALU" in m and m.get("GRBM_GUI_ACTIVE"):
-                per.append("VALU busy %.1f %%" % (100 * m["SQ_ACTIVE_INST_VALU"] / 256 / m["GRBM_GUI_ACTIVE"]))
+            if "SQ_INSTS_VALU" in m and m.get("GRBM_GUI_ACTIVE"):
+                # issue share of the VALU ceiling (one wave64 VALU instruction per CU
+                # and clock); GRBM_GUI_ACTIVE is summed over the 8 XCDs
+                per.append("VALU issue %.1f %% of the ceiling" % (100 * m["SQ_INSTS_VALU"] / 256
+                                                                  / (m["GRBM_GUI_ACTIVE"] / 8)))
             extra = "  " + ", ".join(per)
         lines.append("%-44s grid %10d  %s%s" % (k, grid, " ".join("%s=%.4g" % kv for kv in sorted(m.items())), extra))
     return "\n".join(lines)
