@@ -97,8 +97,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
                                                   const typename Storage<T>::R* __restrict__ force_y,
                                                   const void* dL_drho, const void* dL_du, int fdt,
                                                   typename Storage<T>::R* __restrict__ lam,
-                                                  double* __restrict__ partials, Geo g, double rho0,
-                                                  const typename Storage<T>::R* wall) {
+                                                  double* __restrict__ partials, Geo g, double rho0) {
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   const size_t N = (size_t)g.N;
@@ -115,7 +114,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(const T* __restrict__ P, const
         for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(P + q * N + c.cell);
       } else {
         double v[L::Q];
-        load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+        load_post<L, T>(P, flags, has_mask, layout, c, g, v);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) f[q] = R(v[q]);
       }
@@ -450,7 +449,7 @@ hipError_t launch_adjoint_seed(int stencil, int dtype, const void* P, const uint
     using R = typename Storage<T>::R;
     hipLaunchKernelGGL((k_adj_seed<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
                        has_mask, layout, lam_layout, (const R*)force_y, dL_drho, dL_du, field_dtype, (R*)lam,
-                       partials, g, p.rho0, (const R*)p.wall);
+                       partials, g, p.rho0);
     return hipGetLastError();
   });
 }

@@ -124,7 +124,7 @@ hipError_t launch_build_flags(int stencil, const uint8_t* solid, uint8_t* flags,
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_init(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
                                               const void* rho, const void* u, int fdt, Geo g, double rho0,
-                                              int compressible, const typename Storage<T>::R* wall) {
+                                              int compressible) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(512) void k_init(T* P, const uint8_t* __restrict__ 
       v[q] = weight<L>(q) * ((r - rho0) + rr * (3.0 * cu + 4.5 * cu * cu - usq));
     }
   }
-  store_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
 }
 
 hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, int has_mask, int layout,
@@ -155,8 +155,7 @@ hipError_t launch_init(int stencil, int dtype, void* P, const uint8_t* flags, in
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_init<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags, has_mask,
-                         layout, rho, u, field_dtype, g, p.rho0, p.compressible,
-                         (const typename Storage<T>::R*)p.wall);
+                         layout, rho, u, field_dtype, g, p.rho0, p.compressible);
       return hipGetLastError();
     })
   })
@@ -168,14 +167,14 @@ template <class L, class T>
 __global__ __launch_bounds__(512) void k_readout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                  int has_mask, int layout, const typename Storage<T>::R* __restrict__ force_y,
                                                  void* rho_out, void* u_out, int fdt, Geo g, double rho0,
-                                                 int compressible, const typename Storage<T>::R* wall) {
+                                                 int compressible) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double r = 0, ux = 0, uy = 0, uz = 0;
   if (!(has_mask && (flags[c.cell] & 1))) {
     double f[L::Q];
-    load_post<L, T>(P, flags, has_mask, layout, c, g, f, wall, rho0);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, f);
     double d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -206,8 +205,7 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
     LBM_DTYPE_SWITCH(dtype, {
       using R = typename Storage<T>::R;
       hipLaunchKernelGGL((k_readout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, layout, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible,
-                         (const R*)p.wall);
+                         has_mask, layout, (const R*)force_y, rho, u, field_dtype, g, p.rho0, p.compressible);
       return hipGetLastError();
     })
   })
@@ -217,12 +215,12 @@ hipError_t launch_readout(int stencil, int dtype, const void* P, const uint8_t* 
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_conserved(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                    int has_mask, int layout, double* __restrict__ partials, Geo g,
-                                                   double rho0, const typename Storage<T>::R* wall) {
+                                                   double rho0) {
   const CellIdx c = cell_of(g);
   double v[4] = {0, 0, 0, 0};
   if (c.valid && !(has_mask && (flags[c.cell] & 1))) {
     double pf[L::Q];
-    load_post<L, T>(P, flags, has_mask, layout, c, g, pf, wall, rho0);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, pf);
     double d = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -264,7 +262,7 @@ hipError_t launch_conserved(int stencil, int dtype, const void* P, const uint8_t
     using L = decltype(lat);
     using T = decltype(tag);
     hipLaunchKernelGGL((k_conserved<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, layout, partials, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+                       has_mask, layout, partials, g, p.rho0);
     return hipGetLastError();
   };
   auto by_dtype = [&](auto lat) -> hipError_t {
@@ -327,8 +325,7 @@ double* noalloc_scratch(int device) {
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_conserved_strided(const T* __restrict__ P, const uint8_t* __restrict__ flags,
                                                            int has_mask, int layout, double* __restrict__ partials,
-                                                           Geo g, double rho0,
-                                                           const typename Storage<T>::R* wall) {
+                                                           Geo g, double rho0) {
   double v[4] = {0, 0, 0, 0};
   const int64_t nblk = (int64_t)g.nxb * g.ny * g.nz;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -341,7 +338,7 @@ __global__ __launch_bounds__(512) void k_conserved_strided(const T* __restrict__
     c.valid = c.x < g.nx;
     if (!c.valid || (has_mask && (flags[c.cell] & 1))) continue;
     double pf[L::Q];
-    load_post<L, T>(P, flags, has_mask, layout, c, g, pf, wall, rho0);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, pf);
     double d = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -366,7 +363,7 @@ hipError_t launch_conserved_noalloc(int stencil, int dtype, const void* P, const
     using L = decltype(lat);
     using T = decltype(tag);
     hipLaunchKernelGGL((k_conserved_strided<L, T>), dim3((unsigned)nslots), dim3(g.bx), 0, s, (const T*)P, flags,
-                       has_mask, layout, scratch_dev, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+                       has_mask, layout, scratch_dev, g, p.rho0);
     return hipGetLastError();
   };
   auto by_dtype = [&](auto lat) -> hipError_t {
@@ -392,8 +389,7 @@ hipError_t launch_conserved_noalloc(int stencil, int dtype, const void* P, const
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const T* __restrict__ P_solid,
                                                   const uint8_t* __restrict__ flags, int has_mask, int layout,
-                                                  double* __restrict__ out, Geo g, double rho0,
-                                                  const typename Storage<T>::R* wall) {
+                                                  double* __restrict__ out, Geo g, double rho0) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
@@ -402,7 +398,7 @@ __global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) v[q] = (double)Storage<T>::load(P_solid + q * N + c.cell);
   } else {
-    load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+    load_post<L, T>(P, flags, has_mask, layout, c, g, v);
   }
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) out[q * N + c.cell] = v[q] + weight<L>(q) * rho0;
@@ -410,15 +406,14 @@ __global__ __launch_bounds__(512) void k_get_pdfs(const T* __restrict__ P, const
 
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_set_pdfs(T* P, const uint8_t* __restrict__ flags, int has_mask, int layout,
-                                                  const double* __restrict__ in, Geo g, double rho0,
-                                                  const typename Storage<T>::R* wall) {
+                                                  const double* __restrict__ in, Geo g, double rho0) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double v[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) v[q] = in[q * N + c.cell] - weight<L>(q) * rho0;
-  store_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+  store_post<L, T>(P, flags, has_mask, layout, c, g, v);
 }
 
 hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const void* P_solid, const uint8_t* flags,
@@ -426,8 +421,7 @@ hipError_t launch_get_pdfs(int stencil, int dtype, const void* P, const void* P_
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_get_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P,
-                         (const T*)P_solid, flags, has_mask, layout, out, g, p.rho0,
-                         (const typename Storage<T>::R*)p.wall);
+                         (const T*)P_solid, flags, has_mask, layout, out, g, p.rho0);
       return hipGetLastError();
     })
   })
@@ -438,7 +432,7 @@ hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_set_pdfs<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (T*)P, flags,
-                         has_mask, layout, in, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+                         has_mask, layout, in, g, p.rho0);
       return hipGetLastError();
     })
   })
@@ -446,18 +440,16 @@ hipError_t launch_set_pdfs(int stencil, int dtype, void* P, const uint8_t* flags
 
 // --------------------------------------------------------------- relayout
 // Copy a stored state from `layout` into the two-array layout of another
-// buffer, in the storage type (the adjoint tape of the AA pattern).  With
-// resting walls every value is copied bit for bit; a moving-wall term is
-// taken off in FP64 and the result rounded once.
+// buffer, in the storage type (the adjoint tape of the AA pattern); every
+// value is copied bit for bit (each slot holds a post-collision value).
 template <class L, class T>
 __global__ __launch_bounds__(512) void k_relayout(const T* __restrict__ P, const uint8_t* __restrict__ flags,
-                                                  int has_mask, int layout, T* __restrict__ out, Geo g, double rho0,
-                                                  const typename Storage<T>::R* wall) {
+                                                  int has_mask, int layout, T* __restrict__ out, Geo g) {
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
   const size_t N = (size_t)g.N;
   double v[L::Q];
-  load_post<L, T>(P, flags, has_mask, layout, c, g, v, wall, rho0);
+  load_post<L, T>(P, flags, has_mask, layout, c, g, v);
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) store_from_double(out + q * N + c.cell, v[q]);
 }
@@ -467,7 +459,7 @@ hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t*
   LBM_STENCIL_SWITCH(stencil, {
     LBM_DTYPE_SWITCH(dtype, {
       hipLaunchKernelGGL((k_relayout<L, T>), dim3((unsigned)num_blocks(g)), dim3(g.bx), 0, s, (const T*)P, flags,
-                         has_mask, layout, (T*)out, g, p.rho0, (const typename Storage<T>::R*)p.wall);
+                         has_mask, layout, (T*)out, g);
       return hipGetLastError();
     })
   })

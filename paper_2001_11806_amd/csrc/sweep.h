@@ -247,12 +247,23 @@ __global__ __launch_bounds__(512) void k_sweep_aa_even(T* A, const uint8_t* __re
   using R = typename Storage<T>::R;
   const CellIdx c = cell_of(g);
   if (!c.valid) return;
-  if (has_mask && (flags[c.cell] & 1)) return;
+  const int fl = has_mask ? flags[c.cell] : 0;
+  if (fl & 1) return;
   T* row = A + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
   const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(T);
   R f[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) f[q] = Storage<T>::load(at_bytes(row + (size_t)q * (size_t)g.N, ox));
+  if (p.moving && (fl & 2)) {
+    // a bounced slot holds the cell's own outgoing population; the
+    // moving-wall term is added here, on loading, as in the two-array gather
+    LBM_NEIGHBOURS(c, g)
+    const uint32_t m = p.links[c.cell];
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q)
+      if ((m >> q) & 1u)
+        f[q] += wall_term<L>(q, flags[upstream<L>(q, c, g, xm, xp, ym, yp, zm, zp)] >> 1, p.wall, p.rho0);
+  }
   const R F[3] = {force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2]};
   collide<L, M>(f, F, p);
 #pragma unroll
@@ -304,14 +315,9 @@ __global__ __launch_bounds__(512) void k_sweep_aa_odd(T* A, const uint8_t* __res
     // opposite slot; solid cells' slots are never written
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-      if (q > 0 && ((m >> opp<L>(q)) & 1u)) {   // x + c_q is solid
-        // the population that re-enters along opp(q) carries the wall term
-        R v = f[q];
-        if (p.moving)
-          v += wall_term<L>(opp<L>(q), flags[upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp)] >> 1, p.wall,
-                            p.rho0);
-        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, v);
-      } else
+      if (q > 0 && ((m >> opp<L>(q)) & 1u))   // x + c_q is solid: the value re-enters along opp(q), and
+        put<T, NT>(A + (size_t)opp<L>(q) * (size_t)g.N + c.cell, f[q]);   // the even kernel adds the wall term
+      else
         put<T, NT>(at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]),
                    f[q]);
     }
@@ -330,12 +336,13 @@ __device__ __forceinline__ void store_from_double(T* p, double v) {
 //   2  AA, after an odd kernel or after initialisation: slot (x + c_q, q),
 //      or (x, opp q) when x + c_q is solid.
 // Solid cells keep their own slots (x, q) in every layout.
-//   In layout 2 a bounced slot holds the re-entering population, i.e. the
-//   outgoing one plus the moving-wall term, which is removed / added here.
+//   In layout 2 a bounced slot holds the cell's own outgoing population;
+//   the moving-wall term of the population that re-enters from it is added
+//   by the even kernel when it loads the slot (as the two-array gather
+//   does), so every stored value is a post-collision value.
 template <class L, class T>
 __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int has_mask, int layout,
-                                          const CellIdx& c, const Geo& g, double* v,
-                                          const typename Storage<T>::R* wall, double rho0) {
+                                          const CellIdx& c, const Geo& g, double* v) {
   const size_t N = (size_t)g.N;
   const int fl = has_mask ? flags[c.cell] : 0;
   if (layout == 0 || (fl & 1)) {
@@ -351,15 +358,13 @@ __device__ __forceinline__ void load_post(const T* P, const uint8_t* flags, int 
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
       const int fs = (q > 0 && (fl & 2)) ? flags[d] : 0;   // neighbours are read next to walls only
       v[q] = (double)Storage<T>::load((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d);
-      if (fs & 1) v[q] -= (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0);
     }
   }
 }
 
 template <class L, class T>
 __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_mask, int layout, const CellIdx& c,
-                                           const Geo& g, const double* v, const typename Storage<T>::R* wall,
-                                           double rho0) {
+                                           const Geo& g, const double* v) {
   const size_t N = (size_t)g.N;
   const int fl = has_mask ? flags[c.cell] : 0;
   if (layout == 0 || (fl & 1)) {
@@ -374,11 +379,7 @@ __device__ __forceinline__ void store_post(T* P, const uint8_t* flags, int has_m
     for (int q = 0; q < L::Q; ++q) {
       const int d = upstream<L>(opp<L>(q), c, g, xm, xp, ym, yp, zm, zp);  // x + c_q
       const int fs = (q > 0 && (fl & 2)) ? flags[d] : 0;   // neighbours are read next to walls only
-      if (fs & 1)
-        store_from_double(P + opp<L>(q) * N + c.cell,
-                          v[q] + (double)wall_term<L>(opp<L>(q), fs >> 1, wall, (typename Storage<T>::R)rho0));
-      else
-        store_from_double(P + q * N + d, v[q]);
+      store_from_double((fs & 1) ? P + opp<L>(q) * N + c.cell : P + q * N + d, v[q]);
     }
   }
 }

@@ -334,6 +334,52 @@ def test_aa_pattern_equals_two_arrays(stencil, method, dtype):
         g.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("stencil,method", [("D2Q9", "TRT"), ("D3Q19", "MRT"), ("D3Q27", "CUMULANT")])
+def test_aa_equals_two_arrays_with_moving_walls(stencil, method, dtype):
+    """With moving walls (two wall types) the AA pattern still equals the
+    two-array pattern bit for bit in every storage type: a bounced slot
+    holds the cell's own outgoing population and the even kernel adds the
+    moving-wall term when it loads the slot, as the two-array gather does,
+    so no value is rounded once more.  Readout and PDFs after odd and even
+    step counts."""
+    need_gpu()
+    dims, mask, rho, u, F = _setup(stencil, method, dtype)
+    if mask is None:            # the cumulant cases run periodic: give them a resting wall row
+        mask = np.zeros(dims[::-1], dtype=np.uint8)
+        mask[:, 0, :] = 1
+    mask = mask.copy()
+    mask[:, -1, :] = 2
+    pick = np.random.default_rng(23).random(mask.shape)
+    mask[(mask == 1) & (pick < 0.3)] = 3
+    u = u * (mask == 0)
+    table = WALL_TABLE.copy()
+    if stencil == "D2Q9":
+        table[:, 2] = 0
+    rates = _rates(method)
+    print("case AA moving walls", stencil, method, dtype, flush=True)
+    ctxs = []
+    for pattern in (0, 1):
+        g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern)
+        if F is not None and np.ndim(F) == 2:
+            g.set_force(profile=F)
+        elif F is not None:
+            g.set_force(F)
+        for k in (2, 3):
+            g.set_wall_velocity(k, table[k])
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
+        ctxs.append(g)
+    assert torch.equal(ctxs[0].get_pdfs(), ctxs[1].get_pdfs())
+    for chunk in (1, 2, 5, 3):
+        for g in ctxs:
+            g.step(chunk)
+        (ra, ua), (rb, ub) = (g.macroscopic() for g in ctxs)
+        assert torch.equal(ua, ub) and torch.equal(ra, rb), chunk
+        assert torch.equal(ctxs[0].get_pdfs(), ctxs[1].get_pdfs()), chunk
+    for g in ctxs:
+        g.close()
+
+
 def test_aa_set_get_pdfs_roundtrip_and_steps_from_it():
     need_gpu()
     dims, mask, rho, u, F = _setup("D3Q19", "TRT", "f64")
@@ -761,31 +807,51 @@ def test_unstable_run_is_reported_nonfinite(dtype, steps, pattern):
     g.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_streaming_random_solids_match_oracle(dtype):
-    """Lattice above 512 MiB (the streaming path, whose two-array sweep issues
-    a cell's loads together with its flag byte, so solid cells load too) with
-    12 % random solid cells scattered through every wavefront, a wall row and
-    a body force: D3Q19 TRT on 128 x 256 x 224 (1.1 GB per FP64 grid, 558 MB
-    per FP32 grid).  Against the C++ oracle after 3 steps (FP64: every
-    population within 1e-13; FP32 storage: relative L2 of u within 1e-5),
-    and the AA pattern equal to the two-array pattern bit for bit."""
+@pytest.mark.parametrize("stencil,method,dtype,moving", [
+    ("D3Q19", "TRT", "f64", False), ("D3Q19", "TRT", "f32", False), ("D3Q19", "TRT", "f64", True),
+    ("D3Q27", "MRT", "f32", True), ("D3Q27", "CUMULANT", "f16", False)])
+def test_streaming_random_solids_match_oracle(stencil, method, dtype, moving):
+    """Lattices above 512 MiB (the streaming path, whose two-array sweep
+    issues a cell's loads together with its flag byte, so solid cells load
+    too) with 12 % random solid cells scattered through every wavefront, a
+    wall row and a body force (none for the cumulant): D3Q19 TRT on 128 x 256 x 224 (1.1 GB per FP64
+    grid, 558 MB per FP32 grid), D3Q27 MRT FP32 on 128 x 256 x 160 and the
+    D3Q27 cumulant FP16 on 128 x 256 x 320 (566 MB each); with `moving`, a
+    third of the solid cells are moving walls of two types (velocity
+    bounce-back).  Against the C++ oracle with the same storage rounding
+    after 3 steps (FP64: every population within 1e-13; relative L2 of u
+    within 1e-5 for FP32 storage, within the 12-step bound for FP16), and
+    the AA pattern equal to the two-array pattern bit for bit."""
     need_gpu()
     from oracle import cpu as ocpu
-    stencil, method, dims = "D3Q19", "TRT", (128, 256, 224)
-    assert 19 * dims[0] * dims[1] * dims[2] * (8 if dtype == "f64" else 4) > 512 * 2 ** 20
+    eb = {"f64": 8, "f32": 4, "f16": 2}[dtype]
+    dims = (128, 256, 224) if stencil == "D3Q19" else (128, 256, 160 if eb == 4 else 320)
+    Q = 19 if stencil == "D3Q19" else 27
+    assert Q * dims[0] * dims[1] * dims[2] * eb > 512 * 2 ** 20
     mask, rho, u = seeded_fields(stencil, dims, 21)
-    F = np.array([1e-4, -5e-5, 2e-5])
-    rates = _rates(method)
+    table = None
+    if moving:
+        mask = mask.copy()
+        pick = np.random.default_rng(22).random(mask.shape)
+        mask[(mask == 1) & (pick < 1 / 6)] = 2
+        mask[(mask == 1) & (pick > 5 / 6)] = 3
+        table = WALL_TABLE.copy()
+    F = None if method == "CUMULANT" else np.array([1e-4, -5e-5, 2e-5])   # the cumulant runs unforced
+    rates = dict(_rates(method), omega_hi=(1.0,) * 4, omega_bulk=1.0) if method == "CUMULANT" else _rates(method)
     T = 3
     cfg = orun.Config(stencil, method, rates, storage=dtype)
-    P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, rho, u, mask), T, mask, F)
+    P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, rho, u, mask), T, mask, F, table)
     ro, uo = ocpu.readout(cfg, P, mask, F)
     outs = []
     for pattern in (0, 1):
-        print("case random solids", dtype, "pattern", pattern, flush=True)
+        print("case random solids", stencil, method, dtype, "moving" if moving else "resting", "pattern", pattern,
+              flush=True)
         g = make_gpu(stencil, method, dtype, dims, mask, rates, pattern=pattern)
-        g.set_force(F)
+        if F is not None:
+            g.set_force(F)
+        if moving:
+            for k in (2, 3):
+                g.set_wall_velocity(k, table[k])
         g.init_equilibrium(torch.tensor(rho), torch.tensor(u))
         g.step(T)
         outs.append(tuple(to_np(t) for t in g.macroscopic()))
@@ -796,7 +862,7 @@ def test_streaming_random_solids_match_oracle(dtype):
         g.close()
     err = rel_l2(outs[0][1], uo)
     print("rel L2 u %.3e" % err)
-    assert err <= (1e-12 if dtype == "f64" else BOUND_U["f32"])
+    assert err <= (1e-12 if dtype == "f64" else BOUND_U[dtype])
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
