@@ -164,10 +164,12 @@ def test_aa_adjoint_equals_two_arrays(stencil, dtype, T, k, method):
     assert np.array_equal(np.asarray(a[2]), np.asarray(b[2]))
 
 
-def test_aa_adjoint_matches_oracle_with_moving_wall():
-    """AA adjoint against the oracle with a moving wall (the initial
-    checkpoint is relaid out of the AA layout, which rounds the wall term once
-    more, so only to the FP64 bar)."""
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_aa_adjoint_matches_oracle_with_moving_wall(dtype):
+    """AA adjoint with a moving wall: equal bit for bit to the two-array
+    adjoint (the AA slots hold post-collision values, so the initial
+    checkpoint relaid out of the AA layout is an exact copy), and in FP64
+    against the oracle."""
     need_gpu()
     dims = (70, 10, 6)
     mask, rho, u0, F, T = _case("D3Q19", dims)
@@ -176,24 +178,31 @@ def test_aa_adjoint_matches_oracle_with_moving_wall():
     u0 = u0 * (mask == 0)
     table = np.zeros((3, 3))
     table[2] = (0.03, 0.0, 0.01)
-    g = make_gpu("D3Q19", "SRT", "f64", dims, mask, RATES, checkpoint_every=3, max_tape_steps=T, pattern=1)
-    g.set_force(F)
-    g.set_wall_velocity(2, table[2])
-    g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
-    g.step(T)
-    _, u_T = g.macroscopic()
-    dL = torch.zeros_like(u_T)
-    fl = torch.tensor(mask == 0, device=u_T.device)
-    dL[0, :, :, -1] = 2 * u_T[0, :, :, -1] * fl[:, :, -1]
-    g.adjoint_seed(dL)
-    g.adjoint_step(T)
-    du, drho, dF = g.adjoint_grads(want_rho=True)
-    g.close()
-    cfg = orun.Config("D3Q19", "SRT", RATES)
-    L, gu, grho, gF = oadj.gradient(cfg, rho, u0, mask, F, T, wall_velocity=table)
-    assert rel_l2(to_np(du), gu) <= 1e-10
-    assert rel_l2(to_np(drho), grho) <= 1e-10
-    np.testing.assert_allclose(dF, gF, rtol=1e-10)
+    grads = []
+    for pattern in (0, 1):
+        g = make_gpu("D3Q19", "SRT", dtype, dims, mask, RATES, checkpoint_every=3, max_tape_steps=T,
+                     pattern=pattern)
+        g.set_force(F)
+        g.set_wall_velocity(2, table[2])
+        g.init_equilibrium(torch.tensor(rho), torch.tensor(u0))
+        g.step(T)
+        _, u_T = g.macroscopic()
+        dL = torch.zeros_like(u_T)
+        fl = torch.tensor(mask == 0, device=u_T.device)
+        dL[0, :, :, -1] = 2 * u_T[0, :, :, -1] * fl[:, :, -1]
+        g.adjoint_seed(dL)
+        g.adjoint_step(T)
+        grads.append(g.adjoint_grads(want_rho=True))
+        g.close()
+    (du, drho, dF), (du1, drho1, dF1) = grads
+    assert torch.equal(du, du1) and torch.equal(drho, drho1)
+    assert np.array_equal(np.asarray(dF), np.asarray(dF1))
+    if dtype == "f64":
+        cfg = orun.Config("D3Q19", "SRT", RATES)
+        L, gu, grho, gF = oadj.gradient(cfg, rho, u0, mask, F, T, wall_velocity=table)
+        assert rel_l2(to_np(du), gu) <= 1e-10
+        assert rel_l2(to_np(drho), grho) <= 1e-10
+        np.testing.assert_allclose(dF, gF, rtol=1e-10)
 
 
 def test_autograd_function_aa_pattern():
