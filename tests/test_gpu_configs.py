@@ -195,23 +195,29 @@ def test_c2_channel_256_200_steps_f64_vs_f32():
     assert dev < 3e-2
 
 
-def test_c2_channel_streaming_size_200_steps_f64_vs_oracle():
+@pytest.mark.parametrize("nxz", [128, 256])
+def test_c2_channel_streaming_size_200_steps_f64_vs_oracle(nxz, capsys):
     """The C2 recipe (D3Q19 TRT, Lambda 3/16, walls y = 0 and 255, force 1e-6
-    along x, u noise 1e-3, seed 2) on a 128 x 256 x 128 channel: 638 MB per
+    along x, u noise 1e-3, seed 2) on a 128 x 256 x 128 channel (638 MB per
     FP64 grid, above the 512 MiB bound past which the sweep streams with
-    non-temporal stores in the plain block order, as at 256^3.  All 200
-    steps against the C++ oracle computed in long double (the FP64 oracle's
-    own rounding moves u by 3.7e-12 and rho - 1 by 2.4e-9 here,
+    non-temporal stores in the plain block order) and on the full 256^3
+    channel of the benchmark (2.55 GB per grid).  All 200 steps against the
+    C++ oracle computed in long double (the FP64 oracle's own rounding moves
+    u by 3.7e-12 and rho - 1 by 2.4e-9 on the smaller channel,
     ``tests/golden/fp64_oracle_floor.txt``): every stored population within
     1e-13, relative L2 of u within 1e-12, of rho - 1 within 1e-12 or one FP64
     spacing of rho per cell (rho is returned in FP64; |rho - 1| ~ 1e-5)."""
     need_gpu()
-    dims = (128, 256, 128)
+    dims = (nxz, 256, nxz)
     T = 200
-    mask, _, u = inputs.channel_flow(256, seed=2, amp=1e-3, nx=128, nz=128)
+    mask, _, u = inputs.channel_flow(256, seed=2, amp=1e-3, nx=nxz, nz=nxz)
     F = np.array([1e-6, 0.0, 0.0])
     cfg = orun.Config("D3Q19", "TRT", TRT)
-    P = ocpu.run(cfg, ocpu.init_equilibrium(cfg, None, u, mask, precision="ld"), T, mask, F, precision="ld")
+    P = ocpu.init_equilibrium(cfg, None, u, mask, precision="ld")
+    for t0 in range(0, T, 25):   # the long double oracle takes minutes at 256^3: report as it goes
+        P = ocpu.run(cfg, P, 25, mask, F, precision="ld")
+        with capsys.disabled():
+            print("C2 %d^2 x 256 long double oracle: step %d of %d" % (nxz, t0 + 25, T), flush=True)
     ro, uo = ocpu.readout(cfg, P, mask, F, precision="ld")
     g = make_gpu("D3Q19", "TRT", "f64", dims, mask, TRT)
     assert g.Q * g.N * 8 > 512 * 2 ** 20
@@ -225,8 +231,8 @@ def test_c2_channel_streaming_size_200_steps_f64_vs_oracle():
     dP = float(np.max(np.abs((Pg - P).astype(np.float64))))
     eu, er = rel_l2(ug, uo), rel_l2(rg[fl] - 1, ro[fl] - 1)
     br = rho_spacing_bar(ro[fl])
-    print("C2 128x256x128 x %d f64 vs long double oracle: max |dP| %.2e, rel L2 u %.2e, rho-1 %.2e (bar %.2e)"
-          % (T, dP, eu, er, br))
+    print("C2 %dx256x%d x %d f64 vs long double oracle: max |dP| %.2e, rel L2 u %.2e, rho-1 %.2e (bar %.2e)"
+          % (nxz, nxz, T, dP, eu, er, br))
     assert dP <= 1e-13 and eu <= 1e-12 and er <= br
 
 
