@@ -204,7 +204,9 @@ __global__ __launch_bounds__(512) void k_sweep(const T* __restrict__ src, T* __r
 // Single-array AA pattern (Sec. IV-B, Fig. "AA update pattern"), two kernels
 // run alternately.  With P^t the post-collision state of step t:
 //   even kernel (t even -> t+1): the array holds the streamed populations,
-//     A[x][q] = g_q(x); collide in place and store inverted, A[x][opp q] = f*_q(x);
+//     A[x][q] = g_q(x) (from a moving wall: without its wall term, which the
+//     kernel adds on loading); collide in place and store inverted,
+//     A[x][opp q] = f*_q(x);
 //   odd kernel (t odd -> t+1): pull g_q(x) = A[x - c_q][opp q] (bounce-back:
 //     A[x][q] when x - c_q is solid), collide, push f*_q to A[x + c_q][q]
 //     (bounce-back: A[x][opp q] when x + c_q is solid).
