@@ -204,7 +204,9 @@ lbm_status lbm_conserved_noalloc(lbm_ctx* ctx, double* totals_dev);
 
 /* Copy the state out / in as unshifted FP64 PDFs, layout [q*N + i] in the
  * documented direction order.  lbm_set_pdfs rounds into the storage type and
- * resets the step counter and tape; lbm_get_pdfs synchronises. */
+ * resets the step counter; on a context with a tape (checkpoint_every > 0) it
+ * returns LBM_ESTATE, since the adjoint needs the initial fields rho, u that
+ * lbm_init_equilibrium takes.  lbm_get_pdfs synchronises. */
 lbm_status lbm_get_pdfs(lbm_ctx* ctx, double* pdfs_dev);
 lbm_status lbm_set_pdfs(lbm_ctx* ctx, const double* pdfs_dev);
 

@@ -177,6 +177,20 @@ class LBM:
         nx, ny, nz = self.dims
         return (nz, ny, nx)
 
+    def _call(self, fn, *args):
+        """Run an asynchronous library call that reads or writes torch tensors.
+        The lattice's stream first waits for torch's current stream (whose
+        work made the inputs), and the current stream then waits for the
+        lattice's stream, so that no input is freed and reused, and no output
+        read, before the call has run.  Nothing to do when they are one stream."""
+        cur = self.torch.cuda.current_stream(self.device)
+        same = cur == self.stream
+        if not same:
+            self.stream.wait_stream(cur)
+        _check(fn(*args))
+        if not same:
+            cur.wait_stream(self.stream)
+
     def _field(self, t, comps, what):
         torch = self.torch
         if t is None:
@@ -228,8 +242,7 @@ class LBM:
         if r is not None and v is not None and r.dtype != v.dtype:
             r = r.to(v.dtype)
             dt = dv
-        _check(self.lib.lbm_init_equilibrium(self.h, _ptr(r), _ptr(v), dt))
-        self._keep = (r, v)   # keep alive until the stream has consumed them
+        self._call(self.lib.lbm_init_equilibrium, self.h, _ptr(r), _ptr(v), dt)
 
     def step(self, n=1):
         self.generation += 1
@@ -246,7 +259,7 @@ class LBM:
         dtype = dtype or torch.float64
         rho = torch.empty(self._shape3(), dtype=dtype, device=self.device)
         u = torch.empty((3,) + self._shape3(), dtype=dtype, device=self.device)
-        _check(self.lib.lbm_get_macroscopic(self.h, _ptr(rho), _ptr(u), 0 if dtype == torch.float64 else 1))
+        self._call(self.lib.lbm_get_macroscopic, self.h, _ptr(rho), _ptr(u), 0 if dtype == torch.float64 else 1)
         return rho, u
 
     def conserved(self):
@@ -260,21 +273,20 @@ class LBM:
         torch = self.torch
         if out.dtype != torch.float64 or out.numel() < 4 or not out.is_contiguous() or out.device != self.device:
             raise ValueError("out must be a contiguous float64 tensor of >= 4 elements on " + str(self.device))
-        _check(self.lib.lbm_conserved_noalloc(self.h, _ptr(out)))
+        self._call(self.lib.lbm_conserved_noalloc, self.h, _ptr(out))
         return out
 
     def get_pdfs(self):
         torch = self.torch
         P = torch.empty((self.Q,) + self._shape3(), dtype=torch.float64, device=self.device)
-        _check(self.lib.lbm_get_pdfs(self.h, _ptr(P)))
+        self._call(self.lib.lbm_get_pdfs, self.h, _ptr(P))
         return P
 
     def set_pdfs(self, P):
         self.generation += 1
         P, _ = self._field(P, self.Q, "pdfs")
         P = P.to(self.torch.float64).contiguous()
-        _check(self.lib.lbm_set_pdfs(self.h, _ptr(P)))
-        self._keep = (P,)
+        self._call(self.lib.lbm_set_pdfs, self.h, _ptr(P))
 
     # ------------------------------------------------------------ adjoint
     def adjoint_seed(self, dL_du, dL_drho=None):
@@ -282,8 +294,7 @@ class LBM:
         r, _ = self._field(dL_drho, 1, "dL_drho")
         if r is not None:
             r = r.to(g.dtype)
-        _check(self.lib.lbm_adjoint_seed(self.h, _ptr(r), _ptr(g), dt))
-        self._keep_adj = (g, r)
+        self._call(self.lib.lbm_adjoint_seed, self.h, _ptr(r), _ptr(g), dt)
 
     def adjoint_step(self, n):
         _check(self.lib.lbm_adjoint_step(self.h, int(n)))
@@ -294,7 +305,7 @@ class LBM:
         du = torch.empty((3,) + self._shape3(), dtype=dtype, device=self.device)
         dr = torch.empty(self._shape3(), dtype=dtype, device=self.device) if want_rho else None
         dF = (ctypes.c_double * 3)()
-        _check(self.lib.lbm_adjoint_grads(self.h, _ptr(du), _ptr(dr), 0 if dtype == torch.float64 else 1, dF))
+        self._call(self.lib.lbm_adjoint_grads, self.h, _ptr(du), _ptr(dr), 0 if dtype == torch.float64 else 1, dF)
         return du, dr, np.array(list(dF))
 
 

@@ -114,6 +114,8 @@ def test_adjoint_state_errors():
         g.adjoint_step(9)
     with pytest.raises(LBMError, match="t = 0"):
         g.adjoint_grads()
+    with pytest.raises(LBMError, match="LBM_ESTATE.*initial fields"):
+        g.set_pdfs(torch.zeros(19, 4, 6, 64, dtype=torch.float64, device="cuda"))
     g.close()
 
 
