@@ -139,7 +139,7 @@ def main():
 
     import torch
     from paper_2001_11806_amd import inputs
-    from paper_2001_11806_amd.lbm import LBM, copy_q, stream_q
+    from paper_2001_11806_amd.lbm import LBM, copy_q, stream_aa_q, stream_q
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -186,7 +186,7 @@ def main():
     torch.cuda.empty_cache()
 
     if want("copy"):
-        extras.update(bench_copies(torch, copy_q, stream_q, Timer, dev))
+        extras.update(bench_copies(torch, copy_q, stream_q, stream_aa_q, Timer, dev))
 
     if want("c3"):
         # the full 500-step run in every storage type; FP64 on the same GPU
@@ -314,7 +314,9 @@ def main():
 #   copy_*   Q read and Q write SoA streams, element i to element i (the
 #            paper's multi-stream copy benchmark, Sec. V-A, Tab. III);
 #   stream_* the sweep's pull access pattern without its arithmetic:
-#            periodic pull streaming dst[q][x] = src[q][x - c_q].
+#            periodic pull streaming dst[q][x] = src[q][x - c_q];
+#   aa_*     the AA pattern's data movement without arithmetic: its even and
+#            odd in-place kernels alternating on one array.
 # Key -> (kind, stencil, lattice edge, storage, element bytes, waves per CU
 # (0 = full occupancy), threads per block).
 LINES = {
@@ -324,6 +326,7 @@ LINES = {
     # C2 FP64 AA sweeps (full occupancy = 16 waves per CU at their 120-128 VGPRs)
     "copy_q19_f64_256_w16_b256": ("copy", "D3Q19", 256, "f64", 8, 16, 256),
     "stream_d3q19_f64_256_w16_b256": ("stream", "D3Q19", 256, "f64", 8, 16, 256),
+    "aa_d3q19_f64_256_w16_b256": ("aa", "D3Q19", 256, "f64", 8, 16, 256),
     # C2 FP32 two-array sweep (16 waves per CU)
     "copy_q19_f32_256_w16_b256": ("copy", "D3Q19", 256, "f32", 4, 16, 256),
     "stream_d3q19_f32_256_w16_b256": ("stream", "D3Q19", 256, "f32", 4, 16, 256),
@@ -366,9 +369,11 @@ MATCH = {
                              "sweep_d3q27_mrt_512_f16_traffic.txt"),
     "c4_d3q19_srt_adjoint_128_f32": (None, None, "adj_sweep_aa_d3q19_srt_128_f32_traffic.txt"),
 }
+# the AA workload's own access-pattern line
+AA_LINE = {"c2_d3q19_trt_256_f64_aa": "aa_d3q19_f64_256_w16_b256"}
 
 
-def bench_copies(torch, copy_q, stream_q, Timer, dev):
+def bench_copies(torch, copy_q, stream_q, stream_aa_q, Timer, dev):
     """Copy and pull-stream lines of every configured workload, plus two
     copies that owe nothing to this library: hipMemcpyAsync device to device
     (called directly in the HIP runtime torch loaded) and torch's
@@ -380,18 +385,20 @@ def bench_copies(torch, copy_q, stream_q, Timer, dev):
         q = 19 if stencil == "D3Q19" else 27
         N = n ** 3
         src = torch.empty(q * N * eb // 4, dtype=torch.int32, device=dev).fill_(1)
-        dst = torch.empty_like(src)
+        dst = torch.empty_like(src) if kind != "aa" else None
 
-        def run():
+        def run(i):
             if kind == "copy":
                 copy_q(src, dst, N, q, eb, st, waves, block)
-            else:
+            elif kind == "stream":
                 stream_q(src, dst, (n, n, n), stencil, eb, st, waves, block)
-        for _ in range(3):
-            run()
+            else:   # even and odd kernels alternating, in place
+                stream_aa_q(src, (n, n, n), stencil, eb, i & 1, st, waves, block)
+        for i in range(4):
+            run(i)
         with Timer(torch, st) as t:
-            for _ in range(20):
-                run()
+            for i in range(20):
+                run(i)
         gbps = 2 * q * N * eb * 20 / (t.ms / 1e3) / 1e9
         out[key] = {"GBps": gbps, "hbm_frac": gbps * 1e9 / PEAK_HBM}
         log("%s: %.0f GB/s" % (key, gbps))
@@ -441,6 +448,10 @@ def attach_lines(extras):
         if w not in extras:
             continue
         r = extras[w]
+        aline = AA_LINE.get(w)
+        if aline and aline in extras and "achieved_GBps" in r:
+            r["aa_line"] = aline
+            r["frac_of_aa_line"] = r["achieved_GBps"] / extras[aline]["GBps"]
         if line and line in extras and "achieved_GBps" in r:
             r["copy_line"] = line
             r["frac_of_copy_line"] = r["achieved_GBps"] / extras[line]["GBps"]

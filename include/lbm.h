@@ -266,6 +266,21 @@ lbm_status lbm_stream_q(const void* src_dev, void* dst_dev, int32_t nx, int32_t 
                      lbm_stencil stencil, int32_t elem_bytes, int32_t waves_per_cu,
                      int32_t block_threads, void* hip_stream);
 
+/* Bandwidth reference for the AA pattern (Sec. IV-B, Fig. "AA update
+ * pattern"): the data movement of its two in-place kernels with no
+ * collision and no walls, on one buffer buf_dev of Q planes of nx*ny*nz
+ * elements (layout [q][z][y][x]).  phase 0 (even): every cell writes its own
+ * slots back inverted, A[opp q][x] = A[q][x]; phase 1 (odd): every cell reads
+ * A[opp q][x - c_q] and writes it to A[q][x + c_q] (periodic), i.e. plane q
+ * becomes plane opp(q) shifted by 2 c_q.  Launch shape, addressing, block
+ * order and store type are those of the AA sweep; waves_per_cu and
+ * block_threads as in lbm_stream_q.  Errors (LBM_EINVAL, before any device
+ * work): as lbm_stream_q, and phase other than 0 or 1.  hip_stream as in
+ * lbm_create. */
+lbm_status lbm_stream_aa_q(void* buf_dev, int32_t nx, int32_t ny, int32_t nz, lbm_stencil stencil,
+                        int32_t elem_bytes, int32_t phase, int32_t waves_per_cu, int32_t block_threads,
+                        void* hip_stream);
+
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);
 

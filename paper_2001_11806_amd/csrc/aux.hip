@@ -584,6 +584,88 @@ hipError_t launch_stream_q(const void* src, void* dst, int stencil, const Geo& g
   return hipErrorInvalidValue;
 }
 
+// AA-pattern reference: the two in-place kernels of the AA sweep with no
+// collision in between (Sec. IV-B, Fig. "AA update pattern").  The even
+// kernel reads a cell's own slots and writes them back inverted, A[opp q][x]
+// = A[q][x]; the odd kernel reads A[opp q][x - c_q] and writes the value to
+// A[q][x + c_q] (periodic).  Each cell reads exactly the slots it writes, so
+// both are race-free in place, with the AA kernels' addressing, block order
+// and store type.
+template <class L, class E, int ODD, int NT>
+__global__ __launch_bounds__(512) void k_stream_aa_q(E* A, Geo g) {
+  const CellIdx c = cell_of(g);
+  if (!c.valid) return;
+  E v[L::Q];
+  if (!ODD) {
+    E* row = A + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
+    const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(E);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = *at_bytes(row + (size_t)q * (size_t)g.N, ox);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      E* d = at_bytes(row + (size_t)opp<L>(q) * (size_t)g.N, ox);
+      if (NT)
+        __builtin_nontemporal_store(v[q], d);
+      else
+        *d = v[q];
+    }
+  } else {
+    LBM_NEIGHBOURS(c, g)
+    const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(E), (uint32_t)c.x * (uint32_t)sizeof(E),
+                            (uint32_t)xm * (uint32_t)sizeof(E)};  // x - c_x for c_x = -1, 0, +1
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+      v[q] = *at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      E* d = at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]);
+      if (NT)
+        __builtin_nontemporal_store(v[q], d);
+      else
+        *d = v[q];
+    }
+  }
+}
+
+template <class L, class E>
+hipError_t stream_aa_q_typed(void* buf, const Geo& g, int odd, int waves_per_cu, hipStream_t s) {
+  const dim3 grid((unsigned)num_blocks(g)), block(g.bx);
+  const unsigned lds = occupancy_lds(waves_per_cu, g.bx);
+  const bool nt = (size_t)g.N * L::Q * sizeof(E) > kStreamGridBytes;
+  if (odd) {
+    if (nt)
+      hipLaunchKernelGGL((k_stream_aa_q<L, E, 1, 1>), grid, block, lds, s, (E*)buf, g);
+    else
+      hipLaunchKernelGGL((k_stream_aa_q<L, E, 1, 0>), grid, block, lds, s, (E*)buf, g);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((k_stream_aa_q<L, E, 0, 1>), grid, block, lds, s, (E*)buf, g);
+    else
+      hipLaunchKernelGGL((k_stream_aa_q<L, E, 0, 0>), grid, block, lds, s, (E*)buf, g);
+  }
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t stream_aa_q_stencil(void* buf, const Geo& g, int elem_bytes, int odd, int waves_per_cu, hipStream_t s) {
+  switch (elem_bytes) {
+    case 2: return stream_aa_q_typed<L, uint16_t>(buf, g, odd, waves_per_cu, s);
+    case 4: return stream_aa_q_typed<L, uint32_t>(buf, g, odd, waves_per_cu, s);
+    case 8: return stream_aa_q_typed<L, uint64_t>(buf, g, odd, waves_per_cu, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stream_aa_q(void* buf, int stencil, const Geo& g, int elem_bytes, int odd, int waves_per_cu,
+                              hipStream_t s) {
+  switch (stencil) {
+    case 0: return stream_aa_q_stencil<D2Q9>(buf, g, elem_bytes, odd, waves_per_cu, s);
+    case 1: return stream_aa_q_stencil<D3Q19>(buf, g, elem_bytes, odd, waves_per_cu, s);
+    case 2: return stream_aa_q_stencil<D3Q27>(buf, g, elem_bytes, odd, waves_per_cu, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 unsigned occupancy_lds(int waves_per_cu, int block_threads) {
   static int lds_per_cu[64];   // LDS bytes per CU of each device, queried once
   int dev = 0;

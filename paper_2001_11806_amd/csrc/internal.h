@@ -94,6 +94,8 @@ hipError_t launch_copy_q(const void* src, void* dst, int64_t n, int q, int elem_
 // pull-streaming reference over the row-segment launch shape of g
 hipError_t launch_stream_q(const void* src, void* dst, int stencil, const Geo& g, int elem_bytes,
                            int waves_per_cu, hipStream_t s);
+hipError_t launch_stream_aa_q(void* buf, int stencil, const Geo& g, int elem_bytes, int odd, int waves_per_cu,
+                              hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int64_t nparts, int width, double* acc,
                                int accumulate, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);

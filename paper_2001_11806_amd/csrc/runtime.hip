@@ -806,4 +806,33 @@ int32_t lbm_stream_q(const void* src_dev, void* dst_dev, int32_t nx, int32_t ny,
   return LBM_OK;
 }
 
+int32_t lbm_stream_aa_q(void* buf_dev, int32_t nx, int32_t ny, int32_t nz, lbm_stencil stencil, int32_t elem_bytes,
+                        int32_t phase, int32_t waves_per_cu, int32_t block_threads, void* hip_stream) {
+  if (!buf_dev) return fail(LBM_EINVAL, "NULL buffer");
+  if (stencil < 0 || stencil > 2) return fail(LBM_EINVAL, "unknown stencil %d", stencil);
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_EINVAL, "lattice dims must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "lattice has %lld cells; the limit is 2^31 - 1", (long long)N);
+  if (stencil == LBM_D2Q9 && nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return fail(LBM_EINVAL, "elem_bytes must be 2, 4 or 8");
+  if (phase != 0 && phase != 1) return fail(LBM_EINVAL, "phase must be 0 (even) or 1 (odd)");
+  if (waves_per_cu < 0 || waves_per_cu > 32) return fail(LBM_EINVAL, "waves_per_cu must be in 0..32");
+  if (block_threads < 0 || block_threads > 512 || block_threads % 64 != 0)
+    return fail(LBM_EINVAL, "block_threads must be 0 or a multiple of 64 in 64..512");
+  Geo g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.nxb = block_threads ? (nx + block_threads - 1) / block_threads : (nx + 511) / 512;
+  g.bx = block_threads ? block_threads : (((nx + g.nxb - 1) / g.nxb + 63) / 64) * 64;
+  g.N = N;
+  // the AA sweep's block order: direction alternating with the phase, and
+  // XCD slabs on grids within cache reach
+  const size_t bytes = (size_t)N * (size_t)q_of(stencil) * (size_t)elem_bytes;
+  g.order = (bytes <= kStreamGridBytes && num_blocks(g) % 8 == 0 ? 2 : 0) | phase;
+  HIP_TRY(launch_stream_aa_q(buf_dev, stencil, g, elem_bytes, phase, waves_per_cu, (hipStream_t)hip_stream),
+          "stream_aa_q launch");
+  return LBM_OK;
+}
+
 }  // extern "C"

@@ -63,6 +63,7 @@ SIGNATURES = {
     "lbm_conserved_noalloc": ([_P, _P], _I32),
     "lbm_copy_q": ([_P, _P, _I64, _I32, _I32, _I32, _I32, _P], _I32),
     "lbm_stream_q": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P], _I32),
+    "lbm_stream_aa_q": ([_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P], _I32),
     "lbm_last_error": ([], ctypes.c_char_p),
     "lbm_version": ([], _I32),
 }
@@ -325,3 +326,13 @@ def stream_q(src, dst, dims, stencil, elem_bytes, stream, waves_per_cu=0, block_
     nx, ny, nz = (int(d) for d in dims)
     _check(lib.lbm_stream_q(_ptr(src), _ptr(dst), nx, ny, nz, STENCILS[stencil], int(elem_bytes),
                             int(waves_per_cu), int(block_threads), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def stream_aa_q(buf, dims, stencil, elem_bytes, phase, stream, waves_per_cu=0, block_threads=0):
+    """AA-pattern bandwidth reference (see include/lbm.h), in place on buf:
+    phase 0 inverts every cell's slots, phase 1 moves A[opp q][x - c_q] to
+    A[q][x + c_q]; dims = (nx, ny, nz)."""
+    lib = load_library()
+    nx, ny, nz = (int(d) for d in dims)
+    _check(lib.lbm_stream_aa_q(_ptr(buf), nx, ny, nz, STENCILS[stencil], int(elem_bytes), int(phase),
+                               int(waves_per_cu), int(block_threads), ctypes.c_void_p(stream.cuda_stream)))

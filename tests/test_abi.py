@@ -116,6 +116,16 @@ def test_null_arguments(lib):
     assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 33, 0, None) == B.EINVAL     # waves
     assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 0, 100, None) == B.EINVAL    # block
     assert lib.lbm_stream_q(fake, fake, 8, 8, 8, 1, 8, 0, 576, None) == B.EINVAL
+    assert lib.lbm_stream_aa_q(None, 8, 8, 8, 1, 8, 0, 0, 0, None) == B.EINVAL
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 1, 8, 2, 0, 0, None) == B.EINVAL     # phase
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 1, 8, -1, 0, 0, None) == B.EINVAL
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 4, 8, 0, 0, 0, None) == B.EINVAL     # stencil
+    assert lib.lbm_stream_aa_q(fake, 8, 0, 8, 1, 8, 0, 0, 0, None) == B.EINVAL     # dims
+    assert lib.lbm_stream_aa_q(fake, 2048, 2048, 512, 1, 8, 0, 0, 0, None) == B.EINVAL
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 3, 0, 8, 0, 0, 0, None) == B.EINVAL     # D2Q9, nz != 1
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 1, 6, 0, 0, 0, None) == B.EINVAL     # elem_bytes
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 1, 8, 0, 40, 0, None) == B.EINVAL    # waves
+    assert lib.lbm_stream_aa_q(fake, 8, 8, 8, 1, 8, 0, 0, 65, None) == B.EINVAL    # block
     assert lib.lbm_create(None, None, None, None) == B.EINVAL
     assert lib.lbm_version() >= 10000
 
