@@ -309,6 +309,43 @@ def test_c3_cumulant_reduced_multistep_errors():
         g.close()
 
 
+def test_c3_cumulant_384_500_steps_fp32_vs_fp64():
+    """The C3 workload at its full size and configured 500 steps, FP32
+    storage and arithmetic against the FP64 kernel on the same GPU, within
+    the FP32 bar: relative L2 of u <= 1e-5, of rho - 1 <= 5e-5 (5e-8 of
+    rho).  Total mass is conserved in both runs: FP64 to 1e-13; FP32 to
+    1e-8, since unbiased rounding of the stored deviations (|f - w rho0| of
+    order 1e-2, one FP32 rounding per write) moves the total by about 1e-12
+    over 500 steps, while a coherent bias of one FP32 ulp per population
+    every 50 steps would reach 1e-8."""
+    need_gpu()
+    n, T = 384, 500
+    u = inputs.solenoidal_velocity(n, inputs.solenoidal_modes(seed=3), dtype=np.float32)
+    ut = torch.from_numpy(u).cuda()
+    del u
+    res = {}
+    for dtype in ("f64", "f32"):
+        print("case C3 384^3 x %d %s" % (T, dtype), flush=True)
+        g = make_gpu("D3Q27", "CUMULANT", dtype, (n, n, n), None, CUM)
+        g.init_equilibrium(None, ut)
+        m0 = g.conserved()[0]
+        g.step(T)
+        r, uu = g.macroscopic()
+        m1 = g.conserved()[0]
+        g.close()
+        res[dtype] = (r, uu, abs(m1 / m0 - 1))
+    del ut
+    (r64, u64, d64), (r32, u32, d32) = res["f64"], res["f32"]
+    eu = float((u32 - u64).norm() / u64.norm())
+    er = float((r32 - r64).norm() / (r64 - 1).norm())
+    print("C3 384^3 x %d: FP32 vs FP64 rel L2 u %.2e, rho-1 %.2e; mass drift FP64 %.1e, FP32 %.1e"
+          % (T, eu, er, d64, d32), flush=True)
+    del res, r64, u64, r32, u32
+    torch.cuda.empty_cache()
+    assert eu <= 1e-5 and er <= 5e-5
+    assert d64 <= 1e-13 and d32 <= 1e-8
+
+
 # ------------------------------------------------------------------ C4
 def test_c4_adjoint_128_fd_check():
     """D3Q19 SRT 128^3 channel with 5% spheres, F = 1e-5, 200 steps, tape
