@@ -257,6 +257,32 @@ def test_zero_steps_and_set_pdfs_roundtrip():
     g.close()
 
 
+@pytest.mark.parametrize("n", [1290, 941])
+def test_allocation_failure_is_reported_and_leaves_nothing_behind(n):
+    """Lattices whose two PDF grids exceed the device memory (D3Q27 FP64:
+    at 1290^3 cells one grid takes 464 GB and its allocation fails; at 941^3
+    the first 180 GB grid is allocated and the second fails) are refused with
+    LBM_ENOMEM at creation, before any kernel runs; whatever was allocated
+    is released, and the next lattice is created and stepped normally."""
+    need_gpu()
+    from paper_2001_11806_amd.lbm import LBMError
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, total = torch.cuda.mem_get_info()
+    assert n ** 3 < 2 ** 31 and 2 * 27 * 8 * n ** 3 > total
+    with pytest.raises(LBMError, match="LBM_ENOMEM.*hipMalloc"):
+        make_gpu("D3Q27", "SRT", "f64", (n, n, n), None)
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < (64 << 20)
+    dims = (70, 6, 4)
+    g = make_gpu("D3Q19", "TRT", "f64", dims, None)
+    g.init_equilibrium()
+    g.step(3)
+    m = g.conserved()
+    g.close()
+    assert abs(m[0] / (70 * 6 * 4) - 1) < 1e-14
+
+
 def test_x_extent_one_and_wide_rows():
     """nx = 1 (every x-neighbour is the cell itself) and nx > 512 (several
     blocks per row) both match the oracle."""
