@@ -47,3 +47,31 @@ def test_traffic_summary_is_tied_to_the_sources(tmp_path, monkeypatch):
     with open(pkg / "build.py", "a") as f:
         f.write("\n")
     assert bench.read_traffic(name) is None
+
+
+def test_attach_lines_relates_each_workload_to_its_lines(monkeypatch):
+    """Each workload is divided by the copy and pull-stream lines of its own
+    launch shape, and the AA workload also by the AA pattern's line."""
+    monkeypatch.setattr(bench, "read_traffic", lambda name: None)
+    extras = {k: {"GBps": 1000.0 + i} for i, k in enumerate(bench.LINES)}
+    for w in bench.MATCH:
+        extras[w] = {"achieved_GBps": 900.0}
+    bench.attach_lines(extras)
+    for w, (line, sline, _) in bench.MATCH.items():
+        r = extras[w]
+        if line is None:    # the adjoint workload: counters only, no line of its own
+            assert "copy_line" not in r and "stream_line" not in r and r["traffic"] is None
+            continue
+        assert line in bench.LINES and sline in bench.LINES
+        assert r["copy_line"] == line and r["frac_of_copy_line"] == pytest.approx(900.0 / extras[line]["GBps"])
+        assert r["stream_line"] == sline
+        assert r["frac_of_stream_line"] == pytest.approx(900.0 / extras[sline]["GBps"])
+        assert bench.LINES[line][0] == "copy" and bench.LINES[sline][0] == "stream"
+        assert bench.LINES[line][5:] == bench.LINES[sline][5:]     # same waves per CU and block
+        aline = bench.AA_LINE.get(w)
+        if aline:
+            assert bench.LINES[aline][0] == "aa" and bench.LINES[aline][5:] == bench.LINES[sline][5:]
+            assert r["frac_of_aa_line"] == pytest.approx(900.0 / extras[aline]["GBps"])
+        else:
+            assert "frac_of_aa_line" not in r
+        assert r["traffic"] is None
