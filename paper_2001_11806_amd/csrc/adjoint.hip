@@ -325,6 +325,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, c
   if (c.valid && !(fl & 1)) {
     R f[L::Q];
     uint32_t bb = 0;   // bit q: x - c_q is solid (so x + c_opp(q) is solid)
+    load_phase_begin<T>();
     gather<L, T>(P, flags, fl, c, g, f, &bb, p);
     LBM_NEIGHBOURS(c, g)
     const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(R), (uint32_t)c.x * (uint32_t)sizeof(R),
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep_aa(const T* __restrict__ P, c
           if ((bb >> opp<L>(q)) & 1u) lam[q] = *at_bytes(own + (size_t)opp<L>(q) * N, ox[1]);
       }
     }
+    load_phase_end<T>();
     adj_cell<L, M, R>(f, lam, force_y[3 * c.y], force_y[3 * c.y + 1], force_y[3 * c.y + 2], p, dF);
     if (!ODD) {
 #pragma unroll
