@@ -465,6 +465,19 @@ hipError_t launch_relayout(int stencil, int dtype, const void* P, const uint8_t*
   })
 }
 
+// The reference kernels raise their wave priority while they issue their
+// loads where that makes them faster, as the sweeps do: with 2-byte
+// elements (512^3, 27 planes: pull 4.8-5.1 -> 5.6-5.9 TB/s, copy 5.0-5.2 ->
+// 5.4-5.5 TB/s in alternating processes); 4-byte lines were not faster.
+template <class E>
+__device__ __forceinline__ void ref_load_begin() {
+  if (sizeof(E) == 2) __builtin_amdgcn_s_setprio(2);
+}
+template <class E>
+__device__ __forceinline__ void ref_load_end() {
+  if (sizeof(E) == 2) __builtin_amdgcn_s_setprio(0);
+}
+
 // --------------------------------------------------------------- copy-Q
 // Bandwidth reference: same thread layout and access pattern as the sweep
 // (all Q loads, then all Q stores; blocks of the sweep's row length), without
@@ -475,8 +488,10 @@ __global__ __launch_bounds__(512) void k_copy_q(const E* __restrict__ src, E* __
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   E v[Q];
+  ref_load_begin<E>();
 #pragma unroll
   for (int q = 0; q < Q; ++q) v[q] = src[q * n + i];
+  ref_load_end<E>();
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     if (NT)
@@ -538,9 +553,11 @@ __global__ __launch_bounds__(512) void k_stream_q(const E* __restrict__ src, E* 
   const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(E), (uint32_t)c.x * (uint32_t)sizeof(E),
                           (uint32_t)xm * (uint32_t)sizeof(E)};  // source x for c_x = -1, 0, +1
   E v[L::Q];
+  ref_load_begin<E>();
 #pragma unroll
   for (int q = 0; q < L::Q; ++q)
     v[q] = *at_bytes(row_base<L>(src, q, c.y, c.z, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]);
+  ref_load_end<E>();
   E* row = dst + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
@@ -599,8 +616,10 @@ __global__ __launch_bounds__(512) void k_stream_aa_q(E* A, Geo g) {
   if (!ODD) {
     E* row = A + (size_t)(c.z * g.ny + c.y) * (size_t)g.nx;
     const uint32_t ox = (uint32_t)c.x * (uint32_t)sizeof(E);
+    ref_load_begin<E>();
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) v[q] = *at_bytes(row + (size_t)q * (size_t)g.N, ox);
+    ref_load_end<E>();
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       E* d = at_bytes(row + (size_t)opp<L>(q) * (size_t)g.N, ox);
@@ -613,9 +632,11 @@ __global__ __launch_bounds__(512) void k_stream_aa_q(E* A, Geo g) {
     LBM_NEIGHBOURS(c, g)
     const uint32_t ox[3] = {(uint32_t)xp * (uint32_t)sizeof(E), (uint32_t)c.x * (uint32_t)sizeof(E),
                             (uint32_t)xm * (uint32_t)sizeof(E)};  // x - c_x for c_x = -1, 0, +1
+    ref_load_begin<E>();
 #pragma unroll
     for (int q = 0; q < L::Q; ++q)
       v[q] = *at_bytes(plane_row<L>(A, opp<L>(q), q, c, ym, yp, zm, zp, g), ox[L::c(q, 0) + 1]);
+    ref_load_end<E>();
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       E* d = at_bytes(plane_row<L>(A, q, opp<L>(q), c, ym, yp, zm, zp, g), ox[L::c(opp<L>(q), 0) + 1]);
