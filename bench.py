@@ -763,7 +763,7 @@ def pmc_summary(fetch_dir, write_dir, write_files=False):
             hbm = (fk * f_scale + wk * w_scale) * 1024
             with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
                 fh.write("# HBM traffic of %s (one launch)\n" % desc)
-                fh.write("# commands (GPU box, repository root R, TMPDIR=/tmp; one counter per run):\n"
+                fh.write("# commands (MI355X machine, repository root R, TMPDIR=/tmp; one counter per run):\n"
                          "#   rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o fetch -- python $R/bench.py "
                          "--no-cpu-baseline --short --steps 5 --warmup 1 --only copy,fp32,aa,c3,c4,c5\n"
                          "#   rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o write -- python $R/bench.py "
